@@ -1,0 +1,176 @@
+/*
+ * slmgrit.h -- C ABI of the MI355X (gfx950) semi-Lagrangian MGRIT library.
+ *
+ * The library solves the one-step system of periodic linear advection
+ * (De Sterck, Falgout & Krzysik, arXiv 2203.13382):
+ *     u_{n+1} = Phi u_n,  n = 0..nt-1,  u_0 given              (eq. one-step)
+ * for u_t + alpha u_x = 0 on [-1,1) (eq. ad) or
+ *     u_t + alpha u_x + beta u_y = 0 on [-1,1)^2 (eq. ad_2D),
+ * where Phi is a semi-Lagrangian step of order (p, r) (Sec. 2.1 and 4.1),
+ * either by sequential stepping or by linear multilevel MGRIT (Sec. 2.2)
+ * with the modified coarse-grid operator
+ *     Phi_l = [I - diag(sigma_l) D_{p+1}]^{-1} S_{p,r*}(m^l dt)  (eq. Phi_multilevel)
+ * whose coarse departure points are backtracked (Sec. 3.3.1; SM6 in 2D).
+ *
+ * Conventions shared by every call
+ *   - Mesh x_i = -1 + i h, h = 2/nx (y likewise); a spatial slice has
+ *     S = nx (1D) or nx*nx values (2D), x fastest.
+ *   - A space-time array is [(N+1)][S], time index slowest.
+ *   - "T" is the bulk element type of a plan: double for SLM_FP64, float for
+ *     SLM_FP32_BULK.  Departure-point tracing, backtracking, sigma, GMRES
+ *     inner products and residual norms are always FP64.
+ *   - Device pointers are caller-owned, in the plan's device memory, and
+ *     must stay valid for the duration of the call.  All device work of a
+ *     call is enqueued on `stream` (a hipStream_t, 0 = legacy default);
+ *     calls that return solver statistics synchronise that stream.
+ *   - The library never allocates device memory: the caller provides the
+ *     workspace sized by slm_plan_workspace_size().
+ *   - Return codes: SLM_OK (0); positive values are solver outcomes; negative
+ *     values are errors, with a message in slm_last_error().  No C++
+ *     exception crosses this boundary.
+ */
+#ifndef SLMGRIT_H
+#define SLMGRIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One term of a wave-speed field (Sec. 2.1 requires alpha(x,t) computable
+ * anywhere): coef*cos(kx*pi*x+px)*cos(ky*pi*y+py)*cos(kt*pi*t+pt).  A field
+ * is a sum of at most SLM_MAX_TERMS terms. */
+typedef struct { double coef, kx, px, ky, py, kt, pt; } slm_wave_term;
+#define SLM_MAX_TERMS 8
+#define SLM_MAX_LEVELS 24
+
+enum { SLM_RELAX_F = 0, SLM_RELAX_FCF = 1 };            /* Sec. 2.2 */
+enum { SLM_TOL_ABS = 0, SLM_TOL_REL = 1 };
+enum { SLM_FP64 = 0, SLM_FP32_BULK = 1 };
+
+enum {
+    SLM_OK = 0,                /* success / converged */
+    SLM_NOT_CONVERGED = 1,     /* max_iter cycles without meeting tol */
+    SLM_DIVERGED = 2,          /* residual norm non-finite or > 1e3 rho_0 */
+    SLM_STAGNATED = 3,         /* FP32 bulk: ratio > 0.95 for 3 cycles */
+    SLM_EINVAL = -1,           /* invalid argument or descriptor */
+    SLM_EUNSUPPORTED = -2,     /* valid but not supported by this build */
+    SLM_EWORKSPACE = -3,       /* workspace missing or too small */
+    SLM_EHIP = -4,             /* a HIP runtime call failed */
+    SLM_ENOTSETUP = -5         /* slm_plan_setup() has not run */
+};
+
+/* Problem and solver description.  The library copies everything it needs
+ * at slm_plan_create(); the caller keeps ownership of its arrays. */
+typedef struct {
+    int dim;                   /* 1 or 2 */
+    int nx;                    /* nodes per axis, >= 8 (1D: <= 8192, 2D: <= 4096) */
+    int nt;                    /* fine time steps, >= 1 */
+    double dt;                 /* fine time step (> 0) */
+    int p;                     /* interpolation degree 1..5 (MGRIT: odd p only) */
+    int r;                     /* ERK order 1..5 of the departure trace */
+    const slm_wave_term *alpha; int n_alpha;   /* x-speed */
+    const slm_wave_term *beta;  int n_beta;    /* y-speed (2D) */
+    const int *m; int n_m;     /* coarsening factor per level, the last repeats; >= 2 */
+    int max_levels;            /* >= 1; 1 = no coarsening */
+    int coarsest_max_points;   /* stop coarsening once a level has <= this many time points */
+    int relax;                 /* SLM_RELAX_F or SLM_RELAX_FCF */
+    int gmres_kmax;            /* 1..10 GMRES iterations for the B solve (Sec. 3.3) */
+    double gmres_rtol;         /* exit once the relative residual <= rtol; 0 = always kmax */
+    double tol;                /* stop once rho_k < tol (ABS) or tol*rho_0 (REL), Sec. 2.2 */
+    int tol_mode;              /* SLM_TOL_ABS or SLM_TOL_REL */
+    int max_iter;              /* cycle cap, >= 1 */
+    int precision;             /* SLM_FP64 or SLM_FP32_BULK */
+} slm_desc;
+
+typedef struct slm_plan slm_plan;
+
+typedef struct {
+    int iterations;            /* cycles begun; the last met the tolerance if converged */
+    int status;                /* SLM_OK, SLM_NOT_CONVERGED, SLM_DIVERGED, SLM_STAGNATED */
+    int n_levels;
+    double rho0;               /* residual 2-norm after cycle 0's pre-relaxation */
+    double rho_final;          /* the last measured residual 2-norm */
+    double solve_ms;           /* host wall time of slm_solve */
+    long long point_updates;   /* rows of Phi_l applied (relaxation + residual + output), all levels */
+    long long gmres_solves;    /* B solves (coarse steps) */
+    long long gmres_iters;     /* total GMRES iterations */
+} slm_stats;
+
+/* Validate `desc` and build the level hierarchy (Sec. 2.2, 3.4): coarsen by
+ * m_l while the level keeps >= 2 time points, more than
+ * coarsest_max_points points, fewer than max_levels levels and N_l is a
+ * multiple of m_l.  Host only.  *out receives a new plan or NULL. */
+int slm_plan_create(const slm_desc *desc, slm_plan **out);
+void slm_plan_destroy(slm_plan *plan);
+
+/* Device bytes the plan needs: departure displacements and sigma on every
+ * level, coarse-level iterates and right-hand sides, C-point buffers,
+ * reduction scratch. */
+int slm_plan_workspace_size(const slm_plan *plan, size_t *bytes);
+
+/* Level structure: *n_levels, and for l < min(n_levels, cap): N[l] time
+ * steps and m[l] coarsening factor (0 on the coarsest level). */
+int slm_plan_levels(const slm_plan *plan, int *n_levels, int *N, int *m, int cap);
+
+/* Bind the caller's workspace (d_ws, >= workspace_size bytes, 256-byte
+ * aligned, kept alive and unmodified by the caller while the plan is used)
+ * and enqueue the setup: the fine departure points by one ERK step
+ * (Sec. 2.1), then per level the backtracked coarse departure points
+ * (eq. coarse_depart_interp; SM6) and sigma (eqs. varphi_p_multilevel_def,
+ * nu_p_def).  Departure points are stored as displacements in cells,
+ * d = (x_i - xi)/h (and the y analogue). */
+int slm_plan_setup(slm_plan *plan, void *d_ws, size_t bytes, void *stream);
+
+/* Device views of level l's setup arrays inside the workspace:
+ *   *d_disp : [dim][N_l][S] displacements; double, except level 0 of an
+ *             FP32-bulk plan, which is float (*disp_is_f32 = 1);
+ *   *d_sigma: [dim][N_l][S] double sigma vectors (NULL on level 0). */
+int slm_level_arrays(const slm_plan *plan, int level, const void **d_disp,
+                     int *disp_is_f32, const void **d_sigma);
+
+/* out[k] = Phi_l(n0+k) in[k] for k < count: one level-l time step applied to
+ * `count` independent slices (T, [count][S]); n0+count <= N_l.  Level 0 is
+ * the SL step S_{p,r}; level l >= 1 is eq. (Phi_multilevel) / (BEOper_2D)
+ * with GMRES per the descriptor. */
+int slm_apply_phi(slm_plan *plan, int level, int n0, int count,
+                  const void *d_in, void *d_out, void *stream);
+
+/* Batched F/C relaxation sweep on level l (Sec. 2.2), every coarse interval
+ * in parallel.  `mode`:
+ *   SLM_SWEEP_FC  : from C-values c_in [(nc+1)][S] take m steps per interval
+ *                   (F- then C-relaxation); write the new C-values to c_out
+ *                   (c_out[0] = c_in[0]).
+ *   SLM_SWEEP_RES : from c_in take m-1 steps (F-relaxation) and form the
+ *                   C-point residual r_{jm} = g_{jm} + Phi v_{jm-1} - c_in[j]
+ *                   into res [(nc+1)][S] (res[0] untouched); *h_norm (if not
+ *                   NULL) receives ||r||_2 in FP64 (synchronises the stream).
+ *   SLM_SWEEP_F   : F-relaxation writing every point of v [(N+1)][S].
+ * g is the level's right-hand side [(N+1)][S] or NULL for zero. */
+enum { SLM_SWEEP_FC = 0, SLM_SWEEP_RES = 1, SLM_SWEEP_F = 2 };
+int slm_relax(slm_plan *plan, int level, int mode, const void *d_g,
+              const void *d_c_in, void *d_c_out, void *d_res, void *d_v,
+              double *h_norm, void *stream);
+
+/* Sequential stepping u_{n+1} = Phi_0 u_n from d_u0 (T, [S]).  store_all:
+ * d_u receives [(nt+1)][S]; otherwise only u_{nt} ([S]). */
+int slm_step(slm_plan *plan, const void *d_u0, void *d_u, int store_all, void *stream);
+
+/* Linear MGRIT V-cycles (Sec. 2.2; linear variant of SM2) until the
+ * tolerance test of the descriptor.  d_u ([(nt+1)][S], T) is in/out: on
+ * entry its C-points (every m_0-th slice) are the initial iterate, on exit
+ * it holds the approximation of every time point.  d_u0 is u_0.  The
+ * residual history rho_k is written to h_hist[k] for k < hist_cap.  Returns
+ * the stats status (>= 0) or an error (< 0). */
+int slm_solve(slm_plan *plan, const void *d_u0, void *d_u, slm_stats *stats,
+              double *h_hist, int hist_cap, void *stream);
+
+const char *slm_strerror(int code);
+const char *slm_last_error(const slm_plan *plan);   /* plan may be NULL */
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,167 @@
+// slm_common.h -- device building blocks shared by the gfx950 kernels of the
+// semi-Lagrangian MGRIT library (arXiv 2203.13382).  Internal header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "slmgrit.h"
+
+#define SLM_PI 3.14159265358979323846
+#define SLM_KMAX 10          // GMRES iterations, upper bound (Sec. 3.3)
+#define SLM_WAVE 64          // CDNA wavefront width
+#define SLM_MAXB 1024        // largest workgroup
+
+// ---------------------------------------------------------------- problem data
+// A wave-speed field as a sum of separable cosine terms (the ABI's term list).
+struct WaveField {
+    int n;
+    double coef[SLM_MAX_TERMS], kx[SLM_MAX_TERMS], px[SLM_MAX_TERMS];
+    double ky[SLM_MAX_TERMS], py[SLM_MAX_TERMS], kt[SLM_MAX_TERMS], pt[SLM_MAX_TERMS];
+};
+
+__device__ __forceinline__ double wave_eval(const WaveField &f, double x, double y, double t)
+{
+    double s = 0.0;
+    for (int k = 0; k < f.n; ++k)
+        s += f.coef[k] * cos(f.kx[k] * SLM_PI * x + f.px[k]) * cos(f.ky[k] * SLM_PI * y + f.py[k]) *
+             cos(f.kt[k] * SLM_PI * t + f.pt[k]);
+    return s;
+}
+
+// Explicit Runge-Kutta tableaux for the backward departure trace (Sec. 2.1).
+// r=1 forward Euler, r=2 Heun, r=3 Kutta's third-order method, r=4 the
+// classical fourth-order method, r=5 Butcher's six-stage fifth-order method.
+struct Erk {
+    int s;
+    double c[6], b[6], a[6][6];
+};
+
+__host__ __device__ inline Erk erk_tableau(int r)
+{
+    Erk e = {};
+    switch (r) {
+    case 1: e.s = 1; e.b[0] = 1.0; break;
+    case 2: e.s = 2; e.c[1] = 1.0; e.a[1][0] = 1.0; e.b[0] = 0.5; e.b[1] = 0.5; break;
+    case 3:
+        e.s = 3; e.c[1] = 0.5; e.c[2] = 1.0;
+        e.a[1][0] = 0.5; e.a[2][0] = -1.0; e.a[2][1] = 2.0;
+        e.b[0] = 1.0 / 6.0; e.b[1] = 2.0 / 3.0; e.b[2] = 1.0 / 6.0;
+        break;
+    case 4:
+        e.s = 4; e.c[1] = 0.5; e.c[2] = 0.5; e.c[3] = 1.0;
+        e.a[1][0] = 0.5; e.a[2][1] = 0.5; e.a[3][2] = 1.0;
+        e.b[0] = 1.0 / 6.0; e.b[1] = 1.0 / 3.0; e.b[2] = 1.0 / 3.0; e.b[3] = 1.0 / 6.0;
+        break;
+    default:
+        e.s = 6; e.c[1] = 0.25; e.c[2] = 0.25; e.c[3] = 0.5; e.c[4] = 0.75; e.c[5] = 1.0;
+        e.a[1][0] = 0.25;
+        e.a[2][0] = 0.125; e.a[2][1] = 0.125;
+        e.a[3][1] = -0.5; e.a[3][2] = 1.0;
+        e.a[4][0] = 3.0 / 16.0; e.a[4][3] = 9.0 / 16.0;
+        e.a[5][0] = -3.0 / 7.0; e.a[5][1] = 2.0 / 7.0; e.a[5][2] = 12.0 / 7.0;
+        e.a[5][3] = -12.0 / 7.0; e.a[5][4] = 8.0 / 7.0;
+        e.b[0] = 7.0 / 90.0; e.b[2] = 32.0 / 90.0; e.b[3] = 12.0 / 90.0;
+        e.b[4] = 32.0 / 90.0; e.b[5] = 7.0 / 90.0;
+        break;
+    }
+    return e;
+}
+
+// ---------------------------------------------------------------- stencils
+// Offset of the first of the p+1 interpolation nodes relative to the node
+// x_E east of the departure point: -l(p), with the even-p bias of Sec. 2.1
+// (the extra node goes west when eps > 1/2).
+template <typename F>
+__device__ __forceinline__ int stencil_first(int p, F eps)
+{
+    if (p & 1) return -((p + 1) >> 1);
+    return eps > F(0.5) ? -((p >> 1) + 1) : -(p >> 1);
+}
+
+// Lagrange weights of the nodes first+j, j = 0..p, evaluated at -eps, in the
+// shifted variable z = -eps - first (nodes 0..p):
+//   w_j = prod_{k != j} (z - k) / (j - k).
+template <int P, typename F>
+__device__ __forceinline__ void lagrange_weights(F z, F (&w)[P + 1])
+{
+    // 1 / prod_{k != j} (j - k) = (-1)^{P-j} / (j! (P-j)!)
+    constexpr double fact[6] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0};
+    F pre[P + 1], suf[P + 1];
+    pre[0] = F(1);
+#pragma unroll
+    for (int j = 1; j <= P; ++j) pre[j] = pre[j - 1] * (z - F(j - 1));
+    suf[P] = F(1);
+#pragma unroll
+    for (int j = P - 1; j >= 0; --j) suf[j] = suf[j + 1] * (z - F(j + 1));
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        const F inv = F(((P - j) & 1 ? -1.0 : 1.0) / (fact[j] * fact[P - j]));
+        w[j] = pre[j] * suf[j] * inv;
+    }
+}
+
+// f_{p+1}(z) of eq. (fpoly_def), odd p: (1/(p+1)!) prod_{q=-l}^{r} (q + z).
+__device__ __forceinline__ double fpoly_odd(int p, double z)
+{
+    const int l = (p + 1) >> 1, r = (p - 1) >> 1;
+    double prod = 1.0, fact = 1.0;
+    for (int q = -l; q <= r; ++q) prod *= (double)q + z;
+    for (int k = 2; k <= p + 1; ++k) fact *= (double)k;
+    return prod / fact;
+}
+
+// Taps of D_{p+1} = (central second difference)^{(p+1)/2}, odd p
+// (eq. Dp+1_def with a second-order rule): [1,-2,1], [1,-4,6,-4,1],
+// [1,-6,15,-20,15,-6,1].
+template <int P>
+struct DTaps;
+template <> struct DTaps<1> { static constexpr int q = 1; static constexpr double t[3] = {1, -2, 1}; };
+template <> struct DTaps<3> { static constexpr int q = 2; static constexpr double t[5] = {1, -4, 6, -4, 1}; };
+template <> struct DTaps<5> { static constexpr int q = 3; static constexpr double t[7] = {1, -6, 15, -20, 15, -6, 1}; };
+// Even p has no D_{p+1} correction (MGRIT uses odd p only); placeholders keep
+// the stepping-only instantiations well formed.
+template <> struct DTaps<2> { static constexpr int q = 1; static constexpr double t[3] = {0, 0, 0}; };
+template <> struct DTaps<4> { static constexpr int q = 1; static constexpr double t[3] = {0, 0, 0}; };
+
+__device__ __forceinline__ int wrap_mod(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = SLM_WAVE / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, SLM_WAVE);
+    return x;
+}
+
+// Sum NV values over the workgroup; every thread receives the totals.
+// `red` is LDS scratch of 2 * (SLM_MAXB/64) * NV doubles; `buf` alternates
+// between consecutive calls so one barrier per call suffices.  The order of
+// the cross-wave sum is fixed, so results are deterministic and identical in
+// every thread.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *red, int buf)
+{
+    const int lane = threadIdx.x & (SLM_WAVE - 1), wid = threadIdx.x / SLM_WAVE;
+    const int nw = blockDim.x / SLM_WAVE;
+    double *r = red + buf * (SLM_MAXB / SLM_WAVE) * 16;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) r[wid * 16 + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += r[w * 16 + i];
+        v[i] = s;
+    }
+}
+
+#define SLM_RED_DOUBLES (2 * (SLM_MAXB / SLM_WAVE) * 16)

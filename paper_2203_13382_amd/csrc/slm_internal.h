@@ -1,0 +1,79 @@
+// slm_internal.h -- plan structure and kernel launchers (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "slm_common.h"
+
+struct LevelInfo {
+    int N = 0;              // time steps on this level
+    int m = 0;              // coarsening factor to the next level (0: coarsest)
+    size_t disp = 0;        // [dim][N][S] displacements (double; level 0 of bulk: float)
+    size_t disp64 = 0;      // level 0 of an FP32-bulk plan: FP64 copy used by setup
+    size_t sigma = 0;       // [dim][N][S] double, l >= 1
+    size_t V = 0;           // [(N+1)][S] T, l >= 1: iterate
+    size_t G = 0;           // [(N+1)][S] T, l >= 1: right-hand side
+    size_t C = 0;           // [(N/m+1)][S] T: C-point buffer (not on the coarsest level)
+};
+
+struct slm_plan {
+    slm_desc d;                         // copy; pointers below own the arrays
+    std::vector<slm_wave_term> alpha, beta;
+    std::vector<int> mlist;
+    int S = 0;                          // values per spatial slice
+    int L = 0;                          // number of levels
+    LevelInfo lv[SLM_MAX_LEVELS];
+    size_t C0b = 0;                     // second level-0 C-point buffer
+    size_t partial = 0;                 // [max intervals] double
+    size_t norm = 0;                    // 1 double
+    size_t counter = 0;                 // 2 x uint64: gmres solves, iterations
+    size_t ws_bytes = 0;
+    char *ws = nullptr;
+    bool ready = false;
+    int elem = 8;                       // sizeof(T)
+    std::string err;
+    WaveField fa, fb;
+};
+
+// Arguments of the batched relaxation ("chain") kernels: every workgroup
+// advances one coarse interval j through `nsteps` level steps.
+struct ChainArgs {
+    int nx, S, m, nsteps, p;
+    int n_base;              // global step index of chain 0's first step
+    int stride_chain;        // steps between consecutive chains' first steps (= m)
+    const void *disp;        // level displacements [dim][N][S]
+    const double *sigma;     // [dim][N][S] (coarse levels)
+    const void *G;           // [(N+1)][S] or null
+    const void *Cin;         // start slices [(nc+1)][S] (chain j starts at Cin[j]) or null => 0
+    long long cin_stride;    // elements between consecutive start slices
+    void *Vout;              // write every state: Vout[n*S]
+    int write_start;         // also write the start slice at Vout[n_first*S]
+    int write_last;          // also write the final state into Vout
+    void *Cout;              // Cout[(j+cout_shift)*S] = final state
+    int cout_shift;          // 1: C-point sweep (chain 0 also writes Cout[0] = start); 0: direct
+    const void *Cref;        // residual mode: r = final - Cref[(j+1)*S] (null: zero C-values)
+    void *R;                 // residual out R[(j+1)*S]
+    double *partial;         // per-chain sum of r^2
+    int kmax;
+    double rtol;
+    unsigned long long *counter;
+    int nsmall;              // |displacement| bound < nx - p - 1 (cheap wrap)
+};
+
+// launchers (slm_chain1d.hip / slm_setup.hip / slm_misc.hip)
+hipError_t launch_trace_1d(const slm_plan &P, hipStream_t st);
+hipError_t launch_backtrack_1d(const slm_plan &P, int level, hipStream_t st);
+hipError_t launch_chain_1d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);
+hipError_t launch_trace_2d(const slm_plan &P, hipStream_t st);
+hipError_t launch_backtrack_2d(const slm_plan &P, int level, hipStream_t st);
+hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);
+hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st);
+hipError_t launch_axpy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
+                              int count, int S, int elem, int assign, hipStream_t st);
+hipError_t launch_copy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
+                              int count, int S, int elem, hipStream_t st);
+
+inline char *ws_at(const slm_plan &P, size_t off) { return P.ws + off; }

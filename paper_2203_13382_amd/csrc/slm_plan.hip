@@ -1,0 +1,498 @@
+// slm_plan.hip -- C ABI of the library: plan validation and level hierarchy,
+// workspace layout, setup, sequential stepping and the linear MGRIT V-cycle
+// driver (Sec. 2.2; linear variant of SM2).
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "slm_internal.h"
+
+namespace {
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess) return fail(P, SLM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+thread_local std::string g_err;
+
+int fail(slm_plan *P, int code, const std::string &msg)
+{
+    if (P) P->err = msg;
+    g_err = msg;
+    return code;
+}
+int fail(const slm_plan &P, int code, const std::string &msg) { return fail(const_cast<slm_plan *>(&P), code, msg); }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool fill_field(WaveField &f, const slm_wave_term *t, int n)
+{
+    std::memset(&f, 0, sizeof(f));
+    if (n < 0 || n > SLM_MAX_TERMS || (n > 0 && !t)) return false;
+    f.n = n;
+    for (int k = 0; k < n; ++k) {
+        f.coef[k] = t[k].coef; f.kx[k] = t[k].kx; f.px[k] = t[k].px;
+        f.ky[k] = t[k].ky; f.py[k] = t[k].py; f.kt[k] = t[k].kt; f.pt[k] = t[k].pt;
+    }
+    return true;
+}
+
+// Bound on |displacement| in cells of a fine step: dt/h * sum |coef|.
+double disp_bound(const slm_plan &P)
+{
+    double a = 0.0, b = 0.0;
+    for (const auto &t : P.alpha) a += std::fabs(t.coef);
+    for (const auto &t : P.beta) b += std::fabs(t.coef);
+    return P.d.dt / (2.0 / P.d.nx) * (a > b ? a : b);
+}
+
+ChainArgs base_args(const slm_plan &P, int level)
+{
+    ChainArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = P.d.nx;
+    a.S = P.S;
+    a.p = P.d.p;
+    a.m = P.lv[level].m;
+    a.stride_chain = P.lv[level].m;
+    a.disp = ws_at(P, P.lv[level].disp);
+    a.sigma = level > 0 ? (const double *)ws_at(P, P.lv[level].sigma) : nullptr;
+    a.cin_stride = P.S;
+    a.cout_shift = 1;
+    a.kmax = P.d.gmres_kmax;
+    a.rtol = P.d.gmres_rtol;
+    a.counter = (unsigned long long *)ws_at(P, P.counter);
+    a.nsmall = level == 0 && disp_bound(P) + P.d.p + 8 < P.d.nx ? 1 : 0;
+    return a;
+}
+
+hipError_t chain(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
+{
+    return P.d.dim == 1 ? launch_chain_1d(P, level, nchains, a, st) : launch_chain_2d(P, level, nchains, a, st);
+}
+
+struct Solver {
+    slm_plan &P;
+    hipStream_t st;
+    long long updates = 0;
+
+    char *T(size_t off) const { return ws_at(P, off); }
+    size_t sl() const { return (size_t)P.S * P.elem; }
+
+    // Coarse-grid correction of level l >= 1, which starts from a zero
+    // iterate with right-hand side G_l: relax, restrict the C-point
+    // residual by injection, recurse, correct by injection, F-relax.
+    int cycle(int l)
+    {
+        LevelInfo &L = P.lv[l];
+        const int S = P.S;
+        if (l == P.L - 1) {                 // coarsest: sequential stepping
+            ChainArgs a = base_args(P, l);
+            a.m = a.stride_chain = L.N;
+            a.nsteps = L.N;
+            a.G = T(L.G);
+            a.Vout = T(L.V);
+            a.write_start = 1;
+            a.write_last = 1;
+            HIPCHK(chain(P, l, 1, a, st));
+            updates += (long long)L.N * S;
+            return 0;
+        }
+        const int m = L.m, nc = L.N / m;
+        const bool fcf = P.d.relax == SLM_RELAX_FCF;
+        if (fcf) {                          // F- then C-relaxation from zero C-values
+            ChainArgs a = base_args(P, l);
+            a.nsteps = m;
+            a.G = T(L.G);
+            a.Cout = T(L.C);
+            HIPCHK(chain(P, l, nc, a, st));
+            updates += (long long)L.N * S;
+        }
+        {                                   // F-relaxation + C-point residual -> G_{l+1}
+            ChainArgs a = base_args(P, l);
+            a.nsteps = m;
+            a.G = T(L.G);
+            a.Cin = fcf ? T(L.C) : nullptr;
+            a.Cref = fcf ? T(L.C) : nullptr;
+            a.R = T(P.lv[l + 1].G);
+            a.partial = (double *)T(P.partial);
+            HIPCHK(chain(P, l, nc, a, st));
+            updates += (long long)L.N * S;
+        }
+        int rc = cycle(l + 1);
+        if (rc) return rc;
+        HIPCHK(launch_axpy_slices(T(L.C), S, T(P.lv[l + 1].V), S, nc + 1, S, P.elem, fcf ? 0 : 1, st));
+        {                                   // F-relaxation writing every point of V_l
+            ChainArgs a = base_args(P, l);
+            a.nsteps = m - 1;
+            a.G = T(L.G);
+            a.Cin = T(L.C);
+            a.Vout = T(L.V);
+            a.write_start = 1;
+            a.write_last = 1;
+            HIPCHK(chain(P, l, nc, a, st));
+            HIPCHK(launch_copy_slices(T(L.V) + (size_t)L.N * sl(), S, T(L.C) + (size_t)nc * sl(), S, 1, S,
+                                      P.elem, st));
+            updates += (long long)(L.N - nc) * S;
+        }
+        return 0;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------- ABI
+extern "C" {
+
+const char *slm_strerror(int code)
+{
+    switch (code) {
+    case SLM_OK: return "ok";
+    case SLM_NOT_CONVERGED: return "not converged within max_iter cycles";
+    case SLM_DIVERGED: return "diverged";
+    case SLM_STAGNATED: return "stagnated at the FP32 floor";
+    case SLM_EINVAL: return "invalid argument";
+    case SLM_EUNSUPPORTED: return "unsupported";
+    case SLM_EWORKSPACE: return "workspace missing or too small";
+    case SLM_EHIP: return "HIP runtime error";
+    case SLM_ENOTSETUP: return "plan not set up";
+    }
+    return "unknown";
+}
+
+const char *slm_last_error(const slm_plan *plan) { return plan ? plan->err.c_str() : g_err.c_str(); }
+
+int slm_plan_create(const slm_desc *d, slm_plan **out)
+{
+    if (!out) return fail(nullptr, SLM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(nullptr, SLM_EINVAL, "desc is NULL");
+    if (d->dim != 1 && d->dim != 2) return fail(nullptr, SLM_EUNSUPPORTED, "dim must be 1 or 2");
+    if (d->nx < 8 || (d->dim == 1 && d->nx > 8192) || (d->dim == 2 && d->nx > 4096))
+        return fail(nullptr, SLM_EUNSUPPORTED, "nx out of range (1D: 8..8192, 2D: 8..4096)");
+    if (d->nt < 1 || !(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(nullptr, SLM_EINVAL, "nt >= 1 and dt > 0 required");
+    if (d->p < 1 || d->p > 5) return fail(nullptr, SLM_EUNSUPPORTED, "p must be 1..5");
+    if (d->r < 1 || d->r > 5) return fail(nullptr, SLM_EUNSUPPORTED, "r must be 1..5");
+    if (d->n_alpha < 1 || d->n_alpha > SLM_MAX_TERMS || !d->alpha) return fail(nullptr, SLM_EINVAL, "alpha needs 1..8 terms");
+    if (d->dim == 2 && (d->n_beta < 0 || d->n_beta > SLM_MAX_TERMS || (d->n_beta > 0 && !d->beta)))
+        return fail(nullptr, SLM_EINVAL, "beta needs 0..8 terms");
+    if (!d->m || d->n_m < 1) return fail(nullptr, SLM_EINVAL, "m list required");
+    for (int k = 0; k < d->n_m; ++k)
+        if (d->m[k] < 2) return fail(nullptr, SLM_EINVAL, "coarsening factors must be >= 2");
+    if (d->max_levels < 1) return fail(nullptr, SLM_EINVAL, "max_levels >= 1 required");
+    if (d->relax != SLM_RELAX_F && d->relax != SLM_RELAX_FCF) return fail(nullptr, SLM_EINVAL, "relax must be F or FCF");
+    if (d->gmres_kmax < 1 || d->gmres_kmax > SLM_KMAX) return fail(nullptr, SLM_EINVAL, "gmres_kmax must be 1..10");
+    if (!(d->gmres_rtol >= 0.0) || !(d->tol >= 0.0)) return fail(nullptr, SLM_EINVAL, "tolerances must be >= 0");
+    if (d->tol_mode != SLM_TOL_ABS && d->tol_mode != SLM_TOL_REL) return fail(nullptr, SLM_EINVAL, "bad tol_mode");
+    if (d->max_iter < 1) return fail(nullptr, SLM_EINVAL, "max_iter >= 1 required");
+    if (d->precision != SLM_FP64 && d->precision != SLM_FP32_BULK) return fail(nullptr, SLM_EINVAL, "bad precision");
+
+    slm_plan *P = new (std::nothrow) slm_plan();
+    if (!P) return fail(nullptr, SLM_EINVAL, "out of host memory");
+    P->d = *d;
+    P->alpha.assign(d->alpha, d->alpha + d->n_alpha);
+    if (d->dim == 2 && d->n_beta > 0) P->beta.assign(d->beta, d->beta + d->n_beta);
+    P->mlist.assign(d->m, d->m + d->n_m);
+    P->d.alpha = P->alpha.data();
+    P->d.beta = P->beta.empty() ? nullptr : P->beta.data();
+    P->d.n_beta = (int)P->beta.size();
+    P->d.m = P->mlist.data();
+    fill_field(P->fa, P->d.alpha, P->d.n_alpha);
+    fill_field(P->fb, P->d.beta, P->d.n_beta);
+    P->S = d->dim == 1 ? d->nx : d->nx * d->nx;
+    P->elem = d->precision == SLM_FP64 ? 8 : 4;
+
+    // level hierarchy
+    P->L = 1;
+    P->lv[0].N = d->nt;
+    for (int l = 0; l + 1 < SLM_MAX_LEVELS; ++l) {
+        const int m = P->mlist[l < d->n_m ? l : d->n_m - 1];
+        const int N = P->lv[l].N;
+        if (l + 1 >= d->max_levels || N + 1 <= d->coarsest_max_points || N % m != 0 || N / m < 1) break;
+        P->lv[l].m = m;
+        P->lv[l + 1].N = N / m;
+        P->L = l + 2;
+    }
+    P->lv[P->L - 1].m = 0;
+    if (P->L > 1 && (d->p % 2) == 0) {
+        delete P;
+        return fail(nullptr, SLM_EUNSUPPORTED, "MGRIT with the modified coarse operator needs odd p");
+    }
+
+    // workspace layout
+    const size_t S = P->S, el = P->elem, dim = d->dim;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + (bytes ? bytes : 1)); return o; };
+    LevelInfo &L0 = P->lv[0];
+    L0.disp = take(dim * (size_t)d->nt * S * (d->precision == SLM_FP32_BULK ? 4 : 8));
+    if (d->precision == SLM_FP32_BULK) L0.disp64 = take(dim * (size_t)d->nt * S * 8);
+    size_t maxc = 1;
+    if (P->L > 1) {
+        L0.C = take(((size_t)d->nt / L0.m + 1) * S * el);
+        P->C0b = take(((size_t)d->nt / L0.m + 1) * S * el);
+        maxc = d->nt / L0.m;
+    }
+    for (int l = 1; l < P->L; ++l) {
+        LevelInfo &L = P->lv[l];
+        L.disp = take(dim * (size_t)L.N * S * 8);
+        L.sigma = take(dim * (size_t)L.N * S * 8);
+        L.V = take(((size_t)L.N + 1) * S * el);
+        L.G = take(((size_t)L.N + 1) * S * el);
+        if (L.m) {
+            L.C = take(((size_t)L.N / L.m + 1) * S * el);
+            if ((size_t)(L.N / L.m) > maxc) maxc = L.N / L.m;
+        }
+    }
+    P->partial = take(maxc * sizeof(double));
+    P->norm = take(sizeof(double));
+    P->counter = take(2 * sizeof(unsigned long long));
+    P->ws_bytes = off;
+    *out = P;
+    return SLM_OK;
+}
+
+void slm_plan_destroy(slm_plan *plan) { delete plan; }
+
+int slm_plan_workspace_size(const slm_plan *P, size_t *bytes)
+{
+    if (!P || !bytes) return fail(nullptr, SLM_EINVAL, "NULL argument");
+    *bytes = P->ws_bytes;
+    return SLM_OK;
+}
+
+int slm_plan_levels(const slm_plan *P, int *n_levels, int *N, int *m, int cap)
+{
+    if (!P || !n_levels) return fail(nullptr, SLM_EINVAL, "NULL argument");
+    *n_levels = P->L;
+    for (int l = 0; l < P->L && l < cap; ++l) {
+        if (N) N[l] = P->lv[l].N;
+        if (m) m[l] = P->lv[l].m;
+    }
+    return SLM_OK;
+}
+
+int slm_plan_setup(slm_plan *P, void *d_ws, size_t bytes, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!d_ws || bytes < P->ws_bytes) return fail(P, SLM_EWORKSPACE, "workspace smaller than slm_plan_workspace_size()");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(P, SLM_EWORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t st = (hipStream_t)stream;
+    P->ws = (char *)d_ws;
+    P->ready = false;
+    HIPCHK(P->d.dim == 1 ? launch_trace_1d(*P, st) : launch_trace_2d(*P, st));
+    for (int l = 1; l < P->L; ++l) HIPCHK(P->d.dim == 1 ? launch_backtrack_1d(*P, l, st) : launch_backtrack_2d(*P, l, st));
+    P->ready = true;
+    return SLM_OK;
+}
+
+int slm_level_arrays(const slm_plan *P, int level, const void **d_disp, int *disp_is_f32, const void **d_sigma)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(*P, SLM_ENOTSETUP, "plan not set up");
+    if (level < 0 || level >= P->L) return fail(*P, SLM_EINVAL, "level out of range");
+    if (d_disp) *d_disp = ws_at(*P, P->lv[level].disp);
+    if (disp_is_f32) *disp_is_f32 = (level == 0 && P->d.precision == SLM_FP32_BULK) ? 1 : 0;
+    if (d_sigma) *d_sigma = level > 0 ? ws_at(*P, P->lv[level].sigma) : nullptr;
+    return SLM_OK;
+}
+
+int slm_apply_phi(slm_plan *P, int level, int n0, int count, const void *d_in, void *d_out, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (level < 0 || level >= P->L || n0 < 0 || count < 0 || n0 + count > P->lv[level].N)
+        return fail(P, SLM_EINVAL, "level or step range out of bounds");
+    if (count == 0) return SLM_OK;
+    if (!d_in || !d_out) return fail(P, SLM_EINVAL, "NULL slice pointer");
+    ChainArgs a = base_args(*P, level);
+    a.m = 1;
+    a.stride_chain = 1;
+    a.n_base = n0;
+    a.nsteps = 1;
+    a.Cin = d_in;
+    a.Cout = d_out;
+    a.cout_shift = 0;
+    HIPCHK(chain(*P, level, count, a, (hipStream_t)stream));
+    return SLM_OK;
+}
+
+int slm_relax(slm_plan *P, int level, int mode, const void *d_g, const void *d_c_in, void *d_c_out, void *d_res,
+              void *d_v, double *h_norm, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (level < 0 || level >= P->L - 1) return fail(P, SLM_EINVAL, "level must have a coarser level below it");
+    hipStream_t st = (hipStream_t)stream;
+    const LevelInfo &L = P->lv[level];
+    const int m = L.m, nc = L.N / m;
+    ChainArgs a = base_args(*P, level);
+    a.G = d_g;
+    a.Cin = d_c_in;
+    if (mode == SLM_SWEEP_FC) {
+        if (!d_c_out) return fail(P, SLM_EINVAL, "c_out required");
+        a.nsteps = m;
+        a.Cout = d_c_out;
+    } else if (mode == SLM_SWEEP_RES) {
+        if (!d_res) return fail(P, SLM_EINVAL, "res required");
+        a.nsteps = m;
+        a.Cref = d_c_in;
+        a.R = d_res;
+        a.partial = (double *)ws_at(*P, P->partial);
+    } else if (mode == SLM_SWEEP_F) {
+        if (!d_v) return fail(P, SLM_EINVAL, "v required");
+        a.nsteps = m - 1;
+        a.Vout = d_v;
+        a.write_start = 1;
+        a.write_last = 1;
+    } else {
+        return fail(P, SLM_EINVAL, "bad mode");
+    }
+    HIPCHK(chain(*P, level, nc, a, st));
+    if (mode == SLM_SWEEP_F && d_c_in) {
+        HIPCHK(launch_copy_slices((char *)d_v + (size_t)L.N * P->S * P->elem, P->S,
+                                  (const char *)d_c_in + (size_t)nc * P->S * P->elem, P->S, 1, P->S, P->elem, st));
+    }
+    if (mode == SLM_SWEEP_RES && h_norm) {
+        double *dn = (double *)ws_at(*P, P->norm);
+        HIPCHK(launch_sum_partials((double *)ws_at(*P, P->partial), nc, dn, st));
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *h_norm = std::sqrt(v);
+    }
+    return SLM_OK;
+}
+
+int slm_step(slm_plan *P, const void *d_u0, void *d_u, int store_all, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (!d_u0 || !d_u) return fail(P, SLM_EINVAL, "NULL pointer");
+    ChainArgs a = base_args(*P, 0);
+    a.m = a.stride_chain = P->d.nt;
+    a.nsteps = P->d.nt;
+    a.Cin = d_u0;
+    if (store_all) {
+        a.Vout = d_u;
+        a.write_start = 1;
+        a.write_last = 1;
+    } else {
+        a.Cout = d_u;
+        a.cout_shift = 0;
+    }
+    HIPCHK(chain(*P, 0, 1, a, (hipStream_t)stream));
+    return SLM_OK;
+}
+
+int slm_solve(slm_plan *P, const void *d_u0, void *d_u, slm_stats *stats, double *h_hist, int hist_cap,
+              void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (!d_u0 || !d_u) return fail(P, SLM_EINVAL, "NULL pointer");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    const int S = P->S;
+    const size_t sl = (size_t)S * P->elem;
+    char *u = (char *)d_u;
+    slm_stats s;
+    std::memset(&s, 0, sizeof(s));
+    s.n_levels = P->L;
+    HIPCHK(hipMemsetAsync(ws_at(*P, P->counter), 0, 2 * sizeof(unsigned long long), st));
+    Solver sv{*P, st};
+    if (P->L == 1) {                        // no coarsening: sequential stepping
+        int rc = slm_step(P, d_u0, d_u, 1, stream);
+        if (rc) return rc;
+        sv.updates += (long long)P->d.nt * S;
+        s.status = SLM_OK;
+    } else {
+        const int m0 = P->lv[0].m, nc0 = P->d.nt / m0;
+        const bool fcf = P->d.relax == SLM_RELAX_FCF;
+        char *Ca = ws_at(*P, P->lv[0].C), *Cb = ws_at(*P, P->C0b);
+        HIPCHK(launch_copy_slices(Ca, S, u, (long long)m0 * S, nc0 + 1, S, P->elem, st));
+        HIPCHK(launch_copy_slices(Ca, S, d_u0, S, 1, S, P->elem, st));
+        double *dn = (double *)ws_at(*P, P->norm);
+        double rho0 = 0.0;
+        int stag = 0;
+        double prev = 0.0;
+        for (int k = 0;; ++k) {
+            char *Cc = Ca;                 // C-values after pre-relaxation
+            if (fcf) {
+                ChainArgs a = base_args(*P, 0);
+                a.nsteps = m0;
+                a.Cin = Ca;
+                a.Cout = Cb;
+                HIPCHK(chain(*P, 0, nc0, a, st));
+                sv.updates += (long long)P->d.nt * S;
+                Cc = Cb;
+            }
+            {
+                ChainArgs a = base_args(*P, 0);
+                a.nsteps = m0;
+                a.Cin = Cc;
+                a.Cref = Cc;
+                a.R = ws_at(*P, P->lv[1].G);
+                a.partial = (double *)ws_at(*P, P->partial);
+                HIPCHK(chain(*P, 0, nc0, a, st));
+                sv.updates += (long long)P->d.nt * S;
+            }
+            HIPCHK(launch_sum_partials((double *)ws_at(*P, P->partial), nc0, dn, st));
+            double v = 0.0;
+            HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double rho = std::sqrt(v);
+            if (h_hist && k < hist_cap) h_hist[k] = rho;
+            if (k == 0) rho0 = rho;
+            s.iterations = k + 1;
+            s.rho_final = rho;
+            const double thr = P->d.tol_mode == SLM_TOL_REL ? P->d.tol * rho0 : P->d.tol;
+            bool stop = true;
+            if (rho < thr || rho == 0.0) s.status = SLM_OK;
+            else if (!std::isfinite(rho) || rho > 1e3 * rho0) s.status = SLM_DIVERGED;
+            else if (P->d.precision == SLM_FP32_BULK && k > 0 && (stag = rho > 0.95 * prev ? stag + 1 : 0) >= 3)
+                s.status = SLM_STAGNATED;
+            else if (k >= P->d.max_iter) s.status = SLM_NOT_CONVERGED;
+            else stop = false;
+            prev = rho;
+            if (stop) {
+                Ca = Cc;
+                break;
+            }
+            int rc = sv.cycle(1);
+            if (rc) return rc;
+            HIPCHK(launch_axpy_slices(Cc + sl, S, ws_at(*P, P->lv[1].V) + sl, S, nc0, S, P->elem, 0, st));
+            if (fcf) std::swap(Ca, Cb);     // the corrected C-values become the next cycle's start
+        }
+        s.rho0 = rho0;
+        // output: F-relaxation from the final C-values writes every point
+        ChainArgs a = base_args(*P, 0);
+        a.nsteps = m0 - 1;
+        a.Cin = Ca;
+        a.Vout = u;
+        a.write_start = 1;
+        a.write_last = 1;
+        HIPCHK(chain(*P, 0, nc0, a, st));
+        HIPCHK(launch_copy_slices(u + (size_t)P->d.nt * sl, S, Ca + (size_t)nc0 * sl, S, 1, S, P->elem, st));
+        sv.updates += (long long)(P->d.nt - nc0) * S;
+    }
+    unsigned long long cnt[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(cnt, ws_at(*P, P->counter), sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s.gmres_solves = (long long)cnt[0];
+    s.gmres_iters = (long long)cnt[1];
+    s.point_updates = sv.updates;
+    s.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = s;
+    return s.status;
+}
+
+}  // extern "C"
+
+hipError_t launch_chain_2d(const slm_plan &, int, int, const ChainArgs &, hipStream_t)
+{
+    return hipErrorNotSupported;
+}

@@ -1,0 +1,194 @@
+// slm_setup.hip -- plan setup kernels: the fine-grid departure trace and the
+// per-level backtracking of coarse departure points with the sigma recursion.
+//
+// Departure points are stored as displacements in cells, d = (x_i - xi)/h
+// (and (y_j - eta)/h in 2D), so that x_E = x_{i - floor(d)} and
+// eps = d - floor(d) (eq. depart_decompose).
+#include "slm_internal.h"
+
+namespace {
+
+// One ERK step of size dt backwards along the characteristic arriving at
+// (x, y) at time t_arr (eq. depart_ODE; eqs. SL2D_char1-2).  Returns the
+// displacement of the departure point in cells.
+template <int R, int DIM>
+__device__ __forceinline__ void erk_back(const WaveField &fa, const WaveField &fb, double x, double y,
+                                         double t_arr, double dt, double h, double &dx, double &dy)
+{
+    const Erk e = erk_tableau(R);
+    double kx[6], ky[6];
+    const double hs = -dt;
+#pragma unroll
+    for (int s = 0; s < e.s; ++s) {
+        double X = x, Y = y;
+#pragma unroll
+        for (int q = 0; q < s; ++q) {
+            X += hs * e.a[s][q] * kx[q];
+            if (DIM == 2) Y += hs * e.a[s][q] * ky[q];
+        }
+        const double ts = t_arr + e.c[s] * hs;
+        kx[s] = wave_eval(fa, X, Y, ts);
+        ky[s] = DIM == 2 ? wave_eval(fb, X, Y, ts) : 0.0;
+    }
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int s = 0; s < e.s; ++s) {
+        sx += e.b[s] * kx[s];
+        sy += e.b[s] * ky[s];
+    }
+    dx = dt * sx / h;
+    dy = dt * sy / h;
+}
+
+template <int R, int DIM>
+__global__ void trace_kernel(int nx, long long S, int nt, double dt, double h, WaveField fa, WaveField fb,
+                             double *out64, float *out32)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.y;
+    if (id >= S) return;
+    const int i = (int)(id % nx), jy = (int)(id / nx);
+    double dx, dy;
+    erk_back<R, DIM>(fa, fb, -1.0 + i * h, DIM == 2 ? -1.0 + jy * h : 0.0, (n + 1) * dt, dt, h, dx, dy);
+    const long long o = (long long)n * S + id, plane = (long long)nt * S;
+    if (out64) {
+        out64[o] = dx;
+        if (DIM == 2) out64[plane + o] = dy;
+    }
+    if (out32) {
+        out32[o] = (float)dx;
+        if (DIM == 2) out32[plane + o] = (float)dy;
+    }
+}
+
+// Backtracking of Sec. 3.3.1 in displacement form.  The current point of
+// the coarse characteristic is X = i - D (cells).  With E = ceil(X) =
+// i - floor(D) and theta = D - floor(D), the linear interpolant of the
+// sub-step's departure map moves it to X - [(1-theta) d_E + theta d_W].
+// phi (eq. varphi_p_multilevel_def) and sigma (eq. nu_p_def) follow.
+__global__ void backtrack1d_kernel(int nx, int m, int Nl, int p, const double *__restrict__ dprev,
+                                   const double *__restrict__ sprev, double *__restrict__ dcur,
+                                   double *__restrict__ scur)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.y;
+    if (i >= nx || n >= Nl) return;
+    const long long base = (long long)n * m;
+    double D = dprev[(base + m - 1) * nx + i];
+    for (int k = m - 2; k >= 0; --k) {
+        const double fl = floor(D), th = D - fl;
+        const int E = i - (int)fl;
+        const int e = wrap_mod(E, nx), w = wrap_mod(E - 1, nx);
+        const double *dk = dprev + (base + k) * nx;
+        D = D + (1.0 - th) * dk[e] + th * dk[w];
+    }
+    dcur[(long long)n * nx + i] = D;
+    const double sgn = ((p + 1) & 1) ? -1.0 : 1.0;
+    double fs = 0.0, acc = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double dk = dprev[(base + k) * nx + i];
+        fs += fpoly_odd(p, dk - floor(dk));
+        if (sprev) acc += sprev[(base + k) * nx + i];
+    }
+    scur[(long long)n * nx + i] = acc + sgn * (fpoly_odd(p, D - floor(D)) - fs);
+}
+
+// 2D backtracking (SM6): bilinear fit over the cell (W..E) x (S..N) around
+// the current point of how the four neighbouring fine characteristics move
+// their arrival point, separately for the x and y components.  With
+// theta_x = Dx - floor(Dx), theta_y = Dy - floor(Dy) the fit is the tensor
+// product of the 1D weights (1-theta, theta) on (E, W) and (N, S).
+__global__ void backtrack2d_kernel(int nx, int m, int Nl, int p, const double *__restrict__ dprev,
+                                   const double *__restrict__ sprev, double *__restrict__ dcur,
+                                   double *__restrict__ scur, long long plane_prev, long long plane_cur)
+{
+    const long long S = (long long)nx * nx;
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.y;
+    if (id >= S || n >= Nl) return;
+    const int i = (int)(id % nx), jy = (int)(id / nx);
+    const long long base = (long long)n * m;
+    const double *px = dprev, *py = dprev + plane_prev;
+    double Dx = px[(base + m - 1) * S + id], Dy = py[(base + m - 1) * S + id];
+    for (int k = m - 2; k >= 0; --k) {
+        const double fx = floor(Dx), tx = Dx - fx, fy = floor(Dy), ty = Dy - fy;
+        const int E = wrap_mod(i - (int)fx, nx), W = wrap_mod(i - (int)fx - 1, nx);
+        const int N = wrap_mod(jy - (int)fy, nx), Sd = wrap_mod(jy - (int)fy - 1, nx);
+        const double *ax = px + (base + k) * S, *ay = py + (base + k) * S;
+        const long long NE = (long long)N * nx + E, NW = (long long)N * nx + W;
+        const long long SE = (long long)Sd * nx + E, SW = (long long)Sd * nx + W;
+        const double wNE = (1.0 - tx) * (1.0 - ty), wNW = tx * (1.0 - ty);
+        const double wSE = (1.0 - tx) * ty, wSW = tx * ty;
+        const double ddx = wNE * ax[NE] + wNW * ax[NW] + wSE * ax[SE] + wSW * ax[SW];
+        const double ddy = wNE * ay[NE] + wNW * ay[NW] + wSE * ay[SE] + wSW * ay[SW];
+        Dx += ddx;
+        Dy += ddy;
+    }
+    dcur[(long long)n * S + id] = Dx;
+    dcur[plane_cur + (long long)n * S + id] = Dy;
+    const double sgn = ((p + 1) & 1) ? -1.0 : 1.0;
+    double fsx = 0.0, fsy = 0.0, ax = 0.0, ay = 0.0;
+    for (int k = 0; k < m; ++k) {
+        const double dkx = px[(base + k) * S + id], dky = py[(base + k) * S + id];
+        fsx += fpoly_odd(p, dkx - floor(dkx));
+        fsy += fpoly_odd(p, dky - floor(dky));
+        if (sprev) {
+            ax += sprev[(base + k) * S + id];
+            ay += sprev[plane_prev + (base + k) * S + id];
+        }
+    }
+    scur[(long long)n * S + id] = ax + sgn * (fpoly_odd(p, Dx - floor(Dx)) - fsx);
+    scur[plane_cur + (long long)n * S + id] = ay + sgn * (fpoly_odd(p, Dy - floor(Dy)) - fsy);
+}
+
+template <int DIM>
+hipError_t trace_dispatch(const slm_plan &P, hipStream_t st)
+{
+    const LevelInfo &L0 = P.lv[0];
+    const bool f32 = P.d.precision == SLM_FP32_BULK;
+    double *o64 = (double *)ws_at(P, f32 ? L0.disp64 : L0.disp);
+    float *o32 = f32 ? (float *)ws_at(P, L0.disp) : nullptr;
+    const double h = 2.0 / P.d.nx;
+    dim3 grid((unsigned)((P.S + 255) / 256), (unsigned)P.d.nt);
+    switch (P.d.r) {
+    case 1: hipLaunchKernelGGL((trace_kernel<1, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
+    case 2: hipLaunchKernelGGL((trace_kernel<2, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
+    case 3: hipLaunchKernelGGL((trace_kernel<3, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
+    case 4: hipLaunchKernelGGL((trace_kernel<4, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
+    default: hipLaunchKernelGGL((trace_kernel<5, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
+    }
+    return hipGetLastError();
+}
+
+// FP64 displacement array of level l as read by setup.
+const double *setup_disp(const slm_plan &P, int l)
+{
+    if (l == 0 && P.d.precision == SLM_FP32_BULK) return (const double *)ws_at(P, P.lv[0].disp64);
+    return (const double *)ws_at(P, P.lv[l].disp);
+}
+
+}  // namespace
+
+hipError_t launch_trace_1d(const slm_plan &P, hipStream_t st) { return trace_dispatch<1>(P, st); }
+hipError_t launch_trace_2d(const slm_plan &P, hipStream_t st) { return trace_dispatch<2>(P, st); }
+
+hipError_t launch_backtrack_1d(const slm_plan &P, int l, hipStream_t st)
+{
+    const LevelInfo &prev = P.lv[l - 1], &cur = P.lv[l];
+    dim3 grid((unsigned)((P.d.nx + 255) / 256), (unsigned)cur.N);
+    hipLaunchKernelGGL(backtrack1d_kernel, grid, dim3(256), 0, st, P.d.nx, prev.m, cur.N, P.d.p,
+                       setup_disp(P, l - 1), l > 1 ? (const double *)ws_at(P, prev.sigma) : nullptr,
+                       (double *)ws_at(P, cur.disp), (double *)ws_at(P, cur.sigma));
+    return hipGetLastError();
+}
+
+hipError_t launch_backtrack_2d(const slm_plan &P, int l, hipStream_t st)
+{
+    const LevelInfo &prev = P.lv[l - 1], &cur = P.lv[l];
+    dim3 grid((unsigned)((P.S + 255) / 256), (unsigned)cur.N);
+    hipLaunchKernelGGL(backtrack2d_kernel, grid, dim3(256), 0, st, P.d.nx, prev.m, cur.N, P.d.p,
+                       setup_disp(P, l - 1), l > 1 ? (const double *)ws_at(P, prev.sigma) : nullptr,
+                       (double *)ws_at(P, cur.disp), (double *)ws_at(P, cur.sigma),
+                       (long long)prev.N * P.S, (long long)cur.N * P.S);
+    return hipGetLastError();
+}

@@ -1,0 +1,152 @@
+"""Python front end of the library: a ``Plan`` owns the C plan and a torch
+workspace on the GPU and forwards every call to the HIP library."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+try:
+    import torch
+except ImportError:  # pragma: no cover - torch is required for device memory
+    torch = None
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """One problem (``Problem``), solver settings (``Solver``) and precision
+    ("fp64" or "fp32": FP32 bulk with FP64 tracing and norms)."""
+
+    def __init__(self, problem, solver, precision="fp64", device="cuda"):
+        if torch is None:
+            raise N.NativeError("torch is required for device memory")
+        self.pr, self.sv, self.precision = problem, solver, precision
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.S = problem.nx if problem.dim == 1 else problem.nx * problem.nx
+        desc, self._keep = N.make_desc(problem, solver, precision)
+        self._desc = desc
+        h = C.c_void_p()
+        N.check(N.lib().slm_plan_create(C.byref(desc), C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        N.check(N.lib().slm_plan_workspace_size(self.h, C.byref(nb)), self.h)
+        self.ws_bytes = nb.value
+        nl = C.c_int()
+        Ns = (C.c_int * N.MAX_LEVELS)()
+        ms = (C.c_int * N.MAX_LEVELS)()
+        N.check(N.lib().slm_plan_levels(self.h, C.byref(nl), Ns, ms, N.MAX_LEVELS), self.h)
+        self.L = nl.value
+        self.N = [Ns[i] for i in range(self.L)]
+        self.m = [ms[i] for i in range(self.L)]
+        self.ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                N.lib().slm_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ setup
+    def setup(self, stream=None):
+        if self.ws is None:
+            # over-allocate by 256 bytes and align (the ABI wants 256-byte alignment)
+            self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self._ws_raw.data_ptr()) % 256
+            self.ws = self._ws_raw[off:off + self.ws_bytes]
+        N.check(N.lib().slm_plan_setup(self.h, _ptr(self.ws), self.ws_bytes, _stream(stream)), self.h)
+        return self
+
+    def _view(self, ptr, nbytes, dtype, shape):
+        off = ptr - self.ws.data_ptr()
+        assert 0 <= off and off + nbytes <= self.ws_bytes
+        return self.ws[off:off + nbytes].view(dtype).reshape(shape)
+
+    def level_arrays(self, level):
+        """(displacement [dim][N][S], sigma [dim][N][S] or None) as views of
+        the workspace."""
+        dd, ds = C.c_void_p(), C.c_void_p()
+        f32 = C.c_int()
+        N.check(N.lib().slm_level_arrays(self.h, level, C.byref(dd), C.byref(f32), C.byref(ds)), self.h)
+        dim, Nl = self.pr.dim, self.N[level]
+        dt = torch.float32 if f32.value else torch.float64
+        disp = self._view(dd.value, dim * Nl * self.S * (4 if f32.value else 8), dt, (dim, Nl, self.S))
+        sig = None
+        if ds.value:
+            sig = self._view(ds.value, dim * Nl * self.S * 8, torch.float64, (dim, Nl, self.S))
+        return disp, sig
+
+    # ------------------------------------------------------------ operators
+    def _dev(self, x):
+        x = torch.as_tensor(x)
+        return x.to(device=self.device, dtype=self.dtype).contiguous()
+
+    def apply_phi(self, level, n0, x, stream=None):
+        """out[k] = Phi_level(n0+k) x[k]; x is [count][S]."""
+        x = self._dev(x).reshape(-1, self.S)
+        out = torch.empty_like(x)
+        N.check(N.lib().slm_apply_phi(self.h, level, n0, x.shape[0], _ptr(x), _ptr(out), _stream(stream)), self.h)
+        return out
+
+    def relax(self, level, mode, c_in=None, g=None, stream=None):
+        """One batched relaxation sweep (see slm_relax).  Returns the
+        tensor(s) the sweep writes."""
+        Nl, m = self.N[level], self.m[level]
+        nc = Nl // m
+        cin = None if c_in is None else self._dev(c_in).reshape(nc + 1, self.S)
+        gg = None if g is None else self._dev(g).reshape(Nl + 1, self.S)
+        cout = res = v = None
+        norm = C.c_double(0.0)
+        if mode == "FC":
+            cout = torch.zeros(nc + 1, self.S, dtype=self.dtype, device=self.device)
+        elif mode == "RES":
+            res = torch.zeros(nc + 1, self.S, dtype=self.dtype, device=self.device)
+        else:
+            v = torch.zeros(Nl + 1, self.S, dtype=self.dtype, device=self.device)
+        N.check(N.lib().slm_relax(self.h, level, N.SWEEP[mode], _ptr(gg), _ptr(cin), _ptr(cout), _ptr(res),
+                                  _ptr(v), C.byref(norm), _stream(stream)), self.h)
+        if mode == "FC":
+            return cout
+        if mode == "RES":
+            return res, norm.value
+        return v
+
+    def relax_into(self, level, mode, c_in=None, g=None, c_out=None, res=None, v=None, stream=None):
+        """slm_relax on preallocated device tensors (no allocation; for timing)."""
+        N.check(N.lib().slm_relax(self.h, level, N.SWEEP[mode], _ptr(g), _ptr(c_in), _ptr(c_out), _ptr(res),
+                                  _ptr(v), None, _stream(stream)), self.h)
+
+    def step(self, u0, store_all=True, stream=None):
+        u0 = self._dev(u0).reshape(self.S)
+        shape = (self.pr.nt + 1, self.S) if store_all else (self.S,)
+        u = torch.empty(shape, dtype=self.dtype, device=self.device)
+        N.check(N.lib().slm_step(self.h, _ptr(u0), _ptr(u), int(store_all), _stream(stream)), self.h)
+        return u
+
+    def solve(self, u0, u, hist_cap=512, stream=None):
+        """MGRIT in place on ``u`` ([nt+1][S] device tensor whose C-points are
+        the initial iterate).  Returns (stats dict, residual history)."""
+        assert u.dtype == self.dtype and u.is_contiguous() and u.numel() == (self.pr.nt + 1) * self.S
+        u0 = self._dev(u0).reshape(self.S)
+        st = N.Stats()
+        hist = (C.c_double * hist_cap)()
+        rc = N.lib().slm_solve(self.h, _ptr(u0), _ptr(u), C.byref(st), hist, hist_cap, _stream(stream))
+        N.check(rc, self.h)
+        stats = dict(iterations=st.iterations, status=N.STATUS.get(st.status, str(st.status)),
+                     n_levels=st.n_levels, rho0=st.rho0, rho_final=st.rho_final, solve_ms=st.solve_ms,
+                     point_updates=st.point_updates, gmres_solves=st.gmres_solves, gmres_iters=st.gmres_iters)
+        nh = min(hist_cap, st.iterations)
+        return stats, np.array([hist[i] for i in range(nh)])

@@ -1,0 +1,124 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads and
+exports every function declared in include/slmgrit.h, descriptors are
+validated, and the level hierarchy agrees with the oracle's."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2203_13382_amd import _native as N
+from paper_2203_13382_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slmgrit.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(slm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = N.lib()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert {n for n, _, _ in N.SIGNATURES} == set(names)
+
+
+def _create(pr, sv, prec="fp64"):
+    d, keep = N.make_desc(pr, sv, prec)
+    h = C.c_void_p()
+    rc = N.lib().slm_plan_create(C.byref(d), C.byref(h))
+    return rc, h, keep
+
+
+def _levels(h):
+    nl = C.c_int()
+    Ns = (C.c_int * 24)()
+    ms = (C.c_int * 24)()
+    assert N.lib().slm_plan_levels(h, C.byref(nl), Ns, ms, 24) == 0
+    return [Ns[i] for i in range(nl.value)], [ms[i] for i in range(nl.value)]
+
+
+@pytest.mark.parametrize("nt,kw", [
+    (16384, dict(m=[8], coarsest_max_points=16)),
+    (1024, dict(m=[4])),
+    (16384, dict(m=[16, 4])),
+    (256, dict(m=[4], max_levels=2)),
+    (96, dict(m=[8])),
+    (7, dict(m=[2])),
+    (1, dict(m=[2])),
+])
+def test_hierarchy_matches_oracle(oracle, nt, kw):
+    pr = W.Problem(1, 64, nt, 0.05, 3, 3, W.alpha_cfg12())
+    sv = W.Solver(**kw)
+    rc, h, _ = _create(pr, sv)
+    assert rc == 0
+    try:
+        Ns, ms = _levels(h)
+        oN, om = oracle.hierarchy(nt, sv)
+        assert Ns == oN and ms == om
+        nb = C.c_size_t()
+        assert N.lib().slm_plan_workspace_size(h, C.byref(nb)) == 0
+        assert nb.value >= 8 * nt * 64
+    finally:
+        N.lib().slm_plan_destroy(h)
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(dim=3), -2), (dict(nx=4), -2), (dict(nx=9000), -2), (dict(p=6), -2), (dict(r=0), -2),
+    (dict(dt=0.0), -1), (dict(nt=0), -1), (dict(alpha=[]), -1),
+    (dict(p=2), -2),                      # MGRIT needs odd p
+])
+def test_descriptor_validation(change, code):
+    pr = W.Problem(1, 64, 64, 0.05, 3, 3, W.alpha_cfg12())
+    sv = W.Solver(m=[4])
+    for k, v in change.items():
+        setattr(pr, k, v)
+    rc, h, _ = _create(pr, sv)
+    assert rc == code
+    assert not h.value
+    assert len(N.lib().slm_last_error(None)) > 0
+
+
+@pytest.mark.parametrize("change", [dict(m=[1]), dict(gmres_kmax=11), dict(max_iter=0), dict(max_levels=0),
+                                    dict(tol=-1.0)])
+def test_solver_validation(change):
+    pr = W.Problem(1, 64, 64, 0.05, 3, 3, W.alpha_cfg12())
+    sv = W.Solver(m=[4])
+    for k, v in change.items():
+        setattr(sv, k, v)
+    rc, h, _ = _create(pr, sv)
+    assert rc == -1 and not h.value
+
+
+def test_even_p_stepping_only_plan_is_valid():
+    pr = W.Problem(1, 64, 64, 0.05, 2, 2, W.alpha_cfg12())
+    rc, h, _ = _create(pr, W.Solver(m=[4], max_levels=1))
+    assert rc == 0
+    N.lib().slm_plan_destroy(h)
+
+
+def test_calls_before_setup_fail_cleanly():
+    pr = W.Problem(1, 64, 64, 0.05, 3, 3, W.alpha_cfg12())
+    rc, h, _ = _create(pr, W.Solver(m=[4]))
+    assert rc == 0
+    try:
+        st = N.Stats()
+        assert N.lib().slm_solve(h, C.c_void_p(8), C.c_void_p(8), C.byref(st), None, 0, None) == -5
+        assert N.lib().slm_step(h, C.c_void_p(8), C.c_void_p(8), 1, None) == -5
+        assert N.lib().slm_plan_setup(h, None, 0, None) == -3
+        assert N.lib().slm_plan_setup(h, C.c_void_p(1 << 20 | 8), 1 << 40, None) == -3   # misaligned
+        assert b"aligned" in N.lib().slm_last_error(h)
+    finally:
+        N.lib().slm_plan_destroy(h)
+
+
+def test_null_arguments():
+    assert N.lib().slm_plan_create(None, None) == -1
+    assert N.lib().slm_plan_workspace_size(None, None) == -1
+    assert N.lib().slm_strerror(0) == b"ok"
