@@ -5,22 +5,23 @@
 // after it; C-relaxation takes one more step).  All intervals of a level run
 // concurrently.  The spatial slice stays resident in LDS across the steps of
 // an interval, so HBM traffic per point-update is the stored displacement
-// (and the right-hand side on coarse levels) plus the slices a sweep must
-// write.
+// (and the right-hand side on coarse levels) plus the slices a sweep writes.
 //
-// One level step is the semi-Lagrangian step of Sec. 2.1 (level 0) or the
-// modified coarse operator of eq. (Phi_multilevel):
+// Level 0 applies the semi-Lagrangian step of Sec. 2.1; its kernel streams
+// the displacements through a prefetch ring PF steps deep.  Coarse levels
+// apply the modified operator of eq. (Phi_multilevel),
 //     v <- [I - diag(sigma) D_{p+1}]^{-1} S_{p,r*} v,
 // with the inverse applied by GMRES inside the workgroup (Sec. 3.3 / 3.4):
 // zero initial guess, Arnoldi with classical Gram-Schmidt applied twice,
 // Givens rotations, exit once |g_{j+1}| <= rtol*||b|| or after kmax
-// iterations.  Inner products and the Givens recurrence are FP64; the Krylov
-// basis lives in registers (EPT values per thread per vector).
+// iterations.  Inner products and the Givens recurrence are FP64.  The
+// Krylov basis lives in registers (EPT values per thread per vector), so
+// coarse workgroups use at most 512 threads to get 256 VGPRs per lane.
 #include "slm_internal.h"
 
-#include <type_traits>
-
 namespace {
+
+constexpr int COARSE_MAXB = 512;
 
 // Interpolate the LDS slice `s` at the departure point of node i whose
 // displacement is d cells (xi = x_i - d h): x_E = x_{i - floor(d)},
@@ -50,10 +51,134 @@ __device__ __forceinline__ T interp1(const T *__restrict__ s, int i, TD d, int n
     return acc;
 }
 
+// Load the chain's start slice into LDS (and registers); optionally copy it
+// to the full-iterate output and, for chain 0 of a C-point sweep, to Cout[0].
+template <typename T, int EPT>
+__device__ __forceinline__ void chain_start(const ChainArgs &a, T *sl, T (&val)[EPT], long long n_first)
+{
+    const int tid = threadIdx.x, B = blockDim.x, j = blockIdx.x, nx = a.nx;
+    const T *Cin = static_cast<const T *>(a.Cin);
+    T *Vout = static_cast<T *>(a.Vout);
+    T *Cout = static_cast<T *>(a.Cout);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = tid + e * B;
+        T s = T(0);
+        if (i < nx) {
+            if (Cin) s = Cin[(long long)j * a.cin_stride + i];
+            sl[i] = s;
+            if (Vout && a.write_start) Vout[n_first * a.S + i] = s;
+            if (Cout && j == 0 && a.cout_shift) Cout[i] = s;
+        }
+        val[e] = s;
+    }
+}
+
+// Write the chain's final state (Cout) and/or its C-point residual (R) with
+// the per-chain partial sum of squares.
+template <typename T, int EPT>
+__device__ __forceinline__ void chain_finish(const ChainArgs &a, const T (&val)[EPT], double *red, int rb)
+{
+    const int tid = threadIdx.x, B = blockDim.x, j = blockIdx.x, nx = a.nx;
+    const long long S = a.S;
+    T *Cout = static_cast<T *>(a.Cout);
+    if (Cout) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid + e * B;
+            if (i < nx) Cout[(long long)(j + a.cout_shift) * S + i] = val[e];
+        }
+    }
+    if (a.R) {
+        const T *Cref = static_cast<const T *>(a.Cref);
+        T *R = static_cast<T *>(a.R);
+        double acc[1] = {0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid + e * B;
+            if (i < nx) {
+                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
+                R[(long long)(j + 1) * S + i] = r;
+                acc[0] += double(r) * double(r);
+            }
+        }
+        block_sum<1>(acc, red, rb);
+        if (tid == 0) a.partial[j] = acc[0];
+    }
+}
+
+// ------------------------------------------------------------------ level 0
+template <typename T, typename TD, int P, int EPT, bool DBUF, int PF>
+__global__ void __launch_bounds__(SLM_MAXB) fine1d(ChainArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, B = blockDim.x, nx = a.nx;
+    const long long S = a.S;
+    T *sl0 = reinterpret_cast<T *>(smem);
+    T *sl1 = DBUF ? sl0 + nx : sl0;
+    const size_t off = ((size_t)(DBUF ? 2 : 1) * nx * sizeof(T) + 15) & ~size_t(15);
+    double *red = reinterpret_cast<double *>(smem + off);
+    const TD *disp = static_cast<const TD *>(a.disp);
+    const T *G = static_cast<const T *>(a.G);
+    T *Vout = static_cast<T *>(a.Vout);
+    const long long n_first = a.n_base + (long long)blockIdx.x * a.stride_chain;
+    const int ns = a.nsteps;
+
+    T val[EPT];
+    chain_start<T, EPT>(a, sl0, val, n_first);
+    TD ring[PF][EPT];                           // displacements of the next PF steps
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = tid + e * B;
+            ring[u][e] = (u < ns && i < nx) ? disp[(n_first + u) * S + i] : TD(0);
+        }
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < ns; k0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int k = k0 + u;
+            if (k >= ns) break;
+            const long long n = n_first + k;
+            TD dc[EPT];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                dc[e] = ring[u][e];
+                const int i = tid + e * B;
+                if (k + PF < ns && i < nx) ring[u][e] = disp[(n + PF) * S + i];
+            }
+            const T *src = cur ? sl1 : sl0;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int i = tid + e * B;
+                val[e] = i < nx ? interp1<P, T, TD>(src, i, dc[e], nx, a.nsmall) : T(0);
+            }
+            if constexpr (!DBUF) __syncthreads();
+            T *dst = DBUF ? (cur ? sl0 : sl1) : sl0;
+            const bool wv = Vout && (k + 1 < ns || a.write_last);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int i = tid + e * B;
+                if (i < nx) {
+                    if (G) val[e] += G[(n + 1) * S + i];
+                    dst[i] = val[e];
+                    if (wv) Vout[(n + 1) * S + i] = val[e];
+                }
+            }
+            if (DBUF) cur ^= 1;
+            __syncthreads();
+        }
+    }
+    chain_finish<T, EPT>(a, val, red, 0);
+}
+
+// ------------------------------------------------------------------ coarse levels
 // LDS scalars used by thread 0 for the Givens recurrence.
 struct GmresScalars {
     double R[SLM_KMAX][SLM_KMAX];   // R[col][row]
-    double cs[SLM_KMAX], sn[SLM_KMAX], g[SLM_KMAX + 1], z[SLM_KMAX];
+    double cs[SLM_KMAX], sn[SLM_KMAX], g[SLM_KMAX + 1], z[SLM_KMAX], hc[SLM_KMAX + 1];
     int flag;
 };
 
@@ -63,10 +188,10 @@ struct Gmres1D {
     T w[EPT];
     int k;
 
-    // One Arnoldi step JJ.  Returns true when the iteration must stop
-    // before step JJ is taken.
+    // One Arnoldi step JJ.  Returns true when the iteration stops before
+    // step JJ is taken.
     template <int JJ>
-    __device__ __forceinline__ bool step(const double (&sg)[EPT], T *xb, double *red, int &rb,
+    __device__ __forceinline__ bool step(const double *__restrict__ sg, T *xb, double *red, int &rb,
                                           GmresScalars *gs, int kmax, double rtol, double beta, int nx)
     {
         const int tid = threadIdx.x, B = blockDim.x;
@@ -92,15 +217,13 @@ struct Gmres1D {
                     idx -= idx >= nx ? nx : 0;
                     dv += DTaps<P>::t[t + q] * double(xb[idx]);
                 }
-                w[e] = T(double(V[JJ][e]) - sg[e] * dv);
+                w[e] = T(double(V[JJ][e]) - sg[i] * dv);
             } else {
                 w[e] = T(0);
             }
         }
-        // classical Gram-Schmidt, twice
-        double hc[JJ + 1];
-#pragma unroll
-        for (int i = 0; i <= JJ; ++i) hc[i] = 0.0;
+        // classical Gram-Schmidt, twice; the Hessenberg column accumulates
+        // in LDS (thread 0), inner products are wave-uniform
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             double h[JJ + 1];
@@ -111,7 +234,7 @@ struct Gmres1D {
                 for (int e = 0; e < EPT; ++e) s += double(V[i][e]) * double(w[e]);
                 h[i] = s;
             }
-            block_sum<JJ + 1>(h, red, rb);
+            block_sum_u<JJ + 1>(h, red, rb);
             rb ^= 1;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
@@ -120,16 +243,19 @@ struct Gmres1D {
                 for (int i = 0; i <= JJ; ++i) t -= h[i] * double(V[i][e]);
                 w[e] = T(t);
             }
+            if (tid == 0) {
 #pragma unroll
-            for (int i = 0; i <= JJ; ++i) hc[i] += h[i];
+                for (int i = 0; i <= JJ; ++i) gs->hc[i] = pass ? gs->hc[i] + h[i] : h[i];
+            }
         }
         double nn[1] = {0.0};
 #pragma unroll
         for (int e = 0; e < EPT; ++e) nn[0] += double(w[e]) * double(w[e]);
-        block_sum<1>(nn, red, rb);
+        block_sum_u<1>(nn, red, rb);
         rb ^= 1;
         const double hn = sqrt(nn[0]);
         if (tid == 0) {
+            double *hc = gs->hc;
 #pragma unroll
             for (int i = 0; i < JJ; ++i) {          // previous rotations
                 const double t0 = gs->cs[i] * hc[i] + gs->sn[i] * hc[i + 1];
@@ -156,7 +282,7 @@ struct Gmres1D {
     }
 
     // Solve [I - diag(sg) D_{p+1}] y = x in place.  Returns iterations.
-    __device__ __forceinline__ int solve(T (&x)[EPT], const double (&sg)[EPT], T *xb, double *red, int &rb,
+    __device__ __forceinline__ int solve(T (&x)[EPT], const double *__restrict__ sg, T *xb, double *red, int &rb,
                                          GmresScalars *gs, int kmax, double rtol, int nx)
     {
         const int tid = threadIdx.x;
@@ -164,7 +290,7 @@ struct Gmres1D {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) bb[0] += double(x[e]) * double(x[e]);
         if (tid == 0) gs->flag = 0;
-        block_sum<1>(bb, red, rb);
+        block_sum_u<1>(bb, red, rb);
         rb ^= 1;
         const double beta = sqrt(bb[0]);
         if (beta == 0.0 || kmax <= 0) {
@@ -205,162 +331,140 @@ struct Gmres1D {
     }
 };
 
-template <typename T, typename TD, int P, int EPT, bool COARSE, bool DBUF>
-__global__ void __launch_bounds__(SLM_MAXB) chain1d(ChainArgs a)
+template <typename T, int P, int EPT>
+__global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x, B = blockDim.x, nx = a.nx;
     const long long S = a.S;
-    const int j = blockIdx.x;
-    T *sl0 = reinterpret_cast<T *>(smem);
-    T *sl1 = DBUF ? sl0 + nx : sl0;
-    const size_t off = ((size_t)(DBUF ? 2 : 1) * nx * sizeof(T) + 15) & ~size_t(15);
+    T *sl = reinterpret_cast<T *>(smem);
+    const size_t off = ((size_t)nx * sizeof(T) + 15) & ~size_t(15);
     double *red = reinterpret_cast<double *>(smem + off);
     GmresScalars *gs = reinterpret_cast<GmresScalars *>(red + SLM_RED_DOUBLES);
-
-    const T *Cin = static_cast<const T *>(a.Cin);
+    const double *disp = static_cast<const double *>(a.disp);
     const T *G = static_cast<const T *>(a.G);
-    const TD *disp = static_cast<const TD *>(a.disp);
     T *Vout = static_cast<T *>(a.Vout);
-    T *Cout = static_cast<T *>(a.Cout);
-    const long long n_first = a.n_base + (long long)j * a.stride_chain;
+    const long long n_first = a.n_base + (long long)blockIdx.x * a.stride_chain;
 
     T val[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int i = tid + e * B;
-        T s = T(0);
-        if (i < nx) {
-            if (Cin) s = Cin[(long long)j * a.cin_stride + i];
-            sl0[i] = s;
-            if (Vout && a.write_start) Vout[n_first * S + i] = s;
-            if (Cout && j == 0 && a.cout_shift) Cout[i] = s;
-        }
-        val[e] = s;
-    }
+    chain_start<T, EPT>(a, sl, val, n_first);
     __syncthreads();
-
-    TD dn[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int i = tid + e * B;
-        dn[e] = (i < nx && a.nsteps > 0) ? disp[n_first * S + i] : TD(0);
-    }
-    int cur = 0, rb = 0;
+    int rb = 0;
     Gmres1D<T, P, EPT> gm;
     unsigned long long nsolve = 0, niter = 0;
     for (int k = 0; k < a.nsteps; ++k) {
         const long long n = n_first + k;
-        TD dc[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) dc[e] = dn[e];
-        if (k + 1 < a.nsteps) {
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int i = tid + e * B;
-                if (i < nx) dn[e] = disp[(n + 1) * S + i];
-            }
-        }
-        T gv[EPT];
-        double sg[EPT];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = tid + e * B;
-            gv[e] = (G && i < nx) ? G[(n + 1) * S + i] : T(0);
-            sg[e] = (COARSE && i < nx) ? a.sigma[n * S + i] : 0.0;
+            val[e] = i < nx ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
         }
-        const T *src = cur ? sl1 : sl0;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            val[e] = i < nx ? interp1<P, T, TD>(src, i, dc[e], nx, a.nsmall) : T(0);
-        }
-        if constexpr (COARSE) {
-            __syncthreads();                     // every read of the slice is done
-            const int it = gm.solve(val, sg, sl0, red, rb, gs, a.kmax, a.rtol, nx);
-            ++nsolve;
-            niter += it;
-        } else if constexpr (!DBUF) {
-            __syncthreads();
-        }
-        T *dst = DBUF ? (cur ? sl0 : sl1) : sl0;
+        __syncthreads();                         // every read of the slice is done
+        niter += gm.solve(val, a.sigma + n * S, sl, red, rb, gs, a.kmax, a.rtol, nx);
+        ++nsolve;
         const bool wv = Vout && (k + 1 < a.nsteps || a.write_last);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = tid + e * B;
-            val[e] += gv[e];
             if (i < nx) {
-                dst[i] = val[e];
+                if (G) val[e] += G[(n + 1) * S + i];
+                sl[i] = val[e];
                 if (wv) Vout[(n + 1) * S + i] = val[e];
             }
         }
-        if (DBUF) cur ^= 1;
         __syncthreads();
     }
-    if (Cout) {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            if (i < nx) Cout[(long long)(j + a.cout_shift) * S + i] = val[e];
-        }
-    }
-    if (a.R) {
-        const T *Cref = static_cast<const T *>(a.Cref);
-        T *R = static_cast<T *>(a.R);
-        double acc[1] = {0.0};
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            if (i < nx) {
-                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
-                R[(long long)(j + 1) * S + i] = r;
-                acc[0] += double(r) * double(r);
-            }
-        }
-        block_sum<1>(acc, red, rb);
-        if (tid == 0) a.partial[j] = acc[0];
-    }
-    if (COARSE && tid == 0 && a.counter) {
+    chain_finish<T, EPT>(a, val, red, rb);
+    if (tid == 0 && a.counter) {
         atomicAdd(a.counter, nsolve);
         atomicAdd(a.counter + 1, niter);
     }
 }
 
-template <typename T, typename TD, int P, int EPT, bool COARSE, bool DBUF>
-hipError_t launch_one(const ChainArgs &a, int nchains, int block, hipStream_t st)
+// ------------------------------------------------------------------ launchers
+int lds_limit()
 {
-    const size_t sl = ((size_t)(DBUF ? 2 : 1) * a.nx * sizeof(T) + 15) & ~size_t(15);
-    const size_t lds = sl + SLM_RED_DOUBLES * sizeof(double) + sizeof(GmresScalars);
-    auto k = chain1d<T, TD, P, EPT, COARSE, DBUF>;
-    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static int v = -1;
+    if (v < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+    }
+    return v;
+}
+
+template <typename K>
+hipError_t launch(K kern, int nchains, int block, size_t lds, const ChainArgs &a, hipStream_t st)
+{
+    if (lds > (size_t)lds_limit()) return hipErrorInvalidConfiguration;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3(nchains), dim3(block), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(nchains), dim3(block), lds, st, a);
     return hipGetLastError();
 }
 
-template <typename T, typename TD, int P, bool COARSE, bool DBUF>
-hipError_t dispatch_ept(const ChainArgs &a, int nchains, hipStream_t st)
+// Prefetch depth of the displacement ring: about 64 bytes per lane in
+// flight, between 1 and 4 steps.
+template <typename TD, int EPT>
+constexpr int pf_depth()
+{
+    return 64 / ((int)sizeof(TD) * EPT) < 1 ? 1 : (64 / ((int)sizeof(TD) * EPT) > 4 ? 4 : 64 / ((int)sizeof(TD) * EPT));
+}
+
+template <typename T, typename TD, int P, bool DBUF>
+hipError_t fine_ept(const ChainArgs &a, int nchains, hipStream_t st)
 {
     const int block = a.nx >= SLM_MAXB ? SLM_MAXB : ((a.nx + 63) / 64) * 64;
     const int ept = (a.nx + block - 1) / block;
+    const size_t lds = (((size_t)(DBUF ? 2 : 1) * a.nx * sizeof(T) + 15) & ~size_t(15)) +
+                       SLM_RED_DOUBLES * sizeof(double);
     switch (ept) {
-    case 1: return launch_one<T, TD, P, 1, COARSE, DBUF>(a, nchains, block, st);
-    case 2: return launch_one<T, TD, P, 2, COARSE, DBUF>(a, nchains, block, st);
+    case 1: return launch(fine1d<T, TD, P, 1, DBUF, pf_depth<TD, 1>()>, nchains, block, lds, a, st);
+    case 2: return launch(fine1d<T, TD, P, 2, DBUF, pf_depth<TD, 2>()>, nchains, block, lds, a, st);
     case 3:
-    case 4: return launch_one<T, TD, P, 4, COARSE, DBUF>(a, nchains, block, st);
-    default: return launch_one<T, TD, P, 8, COARSE, DBUF>(a, nchains, block, st);
+    case 4: return launch(fine1d<T, TD, P, 4, DBUF, pf_depth<TD, 4>()>, nchains, block, lds, a, st);
+    default: return launch(fine1d<T, TD, P, 8, DBUF, pf_depth<TD, 8>()>, nchains, block, lds, a, st);
     }
 }
 
-template <typename T, typename TD, bool COARSE, bool DBUF>
-hipError_t dispatch_p(const ChainArgs &a, int nchains, hipStream_t st)
+template <typename T, typename TD, bool DBUF>
+hipError_t fine_p(const ChainArgs &a, int nchains, hipStream_t st)
 {
     switch (a.p) {
-    case 1: return dispatch_ept<T, TD, 1, COARSE, DBUF>(a, nchains, st);
-    case 3: return dispatch_ept<T, TD, 3, COARSE, DBUF>(a, nchains, st);
-    case 5: return dispatch_ept<T, TD, 5, COARSE, DBUF>(a, nchains, st);
-    case 2: if constexpr (!COARSE) return dispatch_ept<T, TD, 2, COARSE, DBUF>(a, nchains, st); break;
-    case 4: if constexpr (!COARSE) return dispatch_ept<T, TD, 4, COARSE, DBUF>(a, nchains, st); break;
+    case 1: return fine_ept<T, TD, 1, DBUF>(a, nchains, st);
+    case 2: return fine_ept<T, TD, 2, DBUF>(a, nchains, st);
+    case 3: return fine_ept<T, TD, 3, DBUF>(a, nchains, st);
+    case 4: return fine_ept<T, TD, 4, DBUF>(a, nchains, st);
+    default: return fine_ept<T, TD, 5, DBUF>(a, nchains, st);
+    }
+}
+
+template <typename T, int P>
+hipError_t coarse_ept(const ChainArgs &a, int nchains, hipStream_t st)
+{
+    const int block = a.nx >= COARSE_MAXB ? COARSE_MAXB : ((a.nx + 63) / 64) * 64;
+    const int ept = (a.nx + block - 1) / block;
+    const size_t lds = (((size_t)a.nx * sizeof(T) + 15) & ~size_t(15)) + SLM_RED_DOUBLES * sizeof(double) +
+                       sizeof(GmresScalars);
+    switch (ept) {
+    case 1: return launch(coarse1d<T, P, 1>, nchains, block, lds, a, st);
+    case 2: return launch(coarse1d<T, P, 2>, nchains, block, lds, a, st);
+    case 3:
+    case 4: return launch(coarse1d<T, P, 4>, nchains, block, lds, a, st);
+    case 5: case 6: case 7:
+    case 8: return launch(coarse1d<T, P, 8>, nchains, block, lds, a, st);
+    default: return launch(coarse1d<T, P, 16>, nchains, block, lds, a, st);
+    }
+}
+
+template <typename T>
+hipError_t coarse_p(const ChainArgs &a, int nchains, hipStream_t st)
+{
+    switch (a.p) {
+    case 1: return coarse_ept<T, 1>(a, nchains, st);
+    case 3: return coarse_ept<T, 3>(a, nchains, st);
+    case 5: return coarse_ept<T, 5>(a, nchains, st);
     }
     return hipErrorInvalidValue;
 }
@@ -370,24 +474,11 @@ hipError_t dispatch_p(const ChainArgs &a, int nchains, hipStream_t st)
 hipError_t launch_chain_1d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
 {
     if (nchains <= 0) return hipSuccess;
-    const bool coarse = level > 0;
     const bool f32 = P.d.precision == SLM_FP32_BULK;
+    if (level > 0) return f32 ? coarse_p<float>(a, nchains, st) : coarse_p<double>(a, nchains, st);
     // double-buffer the slice when two copies fit in the workgroup's LDS
-    static int lds_max = -1;
-    if (lds_max < 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-            lds_max = 65536;
-    }
-    const size_t extra = SLM_RED_DOUBLES * sizeof(double) + sizeof(GmresScalars) + 16;
-    const bool dbuf = 2ull * a.nx * (f32 ? 4 : 8) + extra <= (size_t)lds_max;
-    if (coarse) {
-        return f32 ? dispatch_p<float, double, true, false>(a, nchains, st)
-                   : dispatch_p<double, double, true, false>(a, nchains, st);
-    }
-    if (f32) return dbuf ? dispatch_p<float, float, false, true>(a, nchains, st)
-                         : dispatch_p<float, float, false, false>(a, nchains, st);
-    return dbuf ? dispatch_p<double, double, false, true>(a, nchains, st)
-                : dispatch_p<double, double, false, false>(a, nchains, st);
+    const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
+    const bool dbuf = 2ull * a.nx * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
+    if (f32) return dbuf ? fine_p<float, float, true>(a, nchains, st) : fine_p<float, float, false>(a, nchains, st);
+    return dbuf ? fine_p<double, double, true>(a, nchains, st) : fine_p<double, double, false>(a, nchains, st);
 }

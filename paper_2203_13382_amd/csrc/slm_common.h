@@ -131,10 +131,27 @@ __device__ __forceinline__ int wrap_mod(int a, int n)
 }
 
 // ---------------------------------------------------------------- reductions
+// DPP lane permutations (quad_perm xor1, quad_perm xor2, row_half_mirror,
+// row_mirror) applied to both 32-bit halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const unsigned long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wavefront; every lane receives the total.  The
+// four in-row steps use DPP, the two cross-row steps ds_bpermute.
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int off = SLM_WAVE / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, SLM_WAVE);
+    x += dpp_f64<0xB1>(x);    // lanes i ^ 1
+    x += dpp_f64<0x4E>(x);    // lanes i ^ 2
+    x += dpp_f64<0x141>(x);   // the other quad of the 8-lane half row
+    x += dpp_f64<0x140>(x);   // the other half of the 16-lane row
+    x += __shfl_xor(x, 16, SLM_WAVE);
+    x += __shfl_xor(x, 32, SLM_WAVE);
     return x;
 }
 
@@ -165,3 +182,35 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red, int buf)
 }
 
 #define SLM_RED_DOUBLES (2 * (SLM_MAXB / SLM_WAVE) * 16)
+
+__device__ __forceinline__ double readlane_f64(double x, int lane)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// block_sum variant whose totals come back as wave-uniform values (scalar
+// registers): lane l < NV adds up value l over the waves in a fixed order,
+// then each total is read from its lane.  Same determinism as block_sum.
+template <int NV>
+__device__ __forceinline__ void block_sum_u(double (&v)[NV], double *red, int buf)
+{
+    static_assert(NV <= 16, "at most 16 values");
+    const int lane = threadIdx.x & (SLM_WAVE - 1), wid = threadIdx.x / SLM_WAVE;
+    const int nw = blockDim.x / SLM_WAVE;
+    double *r = red + buf * (SLM_MAXB / SLM_WAVE) * 16;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) r[wid * 16 + i] = v[i];
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (lane < NV)
+        for (int w = 0; w < nw; ++w) t += r[w * 16 + lane];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = readlane_f64(t, i);
+}
