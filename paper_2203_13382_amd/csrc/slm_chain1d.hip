@@ -175,10 +175,17 @@ __global__ void __launch_bounds__(SLM_MAXB) fine1d(ChainArgs a)
 }
 
 // ------------------------------------------------------------------ coarse levels
+// Element layout of the coarse kernel: thread t owns the EPT contiguous
+// nodes t*EPT .. t*EPT+EPT-1, so the D_{p+1} stencil needs only q neighbours
+// on each side from other threads.  Those come through an LDS exchange
+// buffer with one pad word per EPT nodes (no bank conflicts).
+template <int EPT>
+__device__ __forceinline__ int pidx(int i) { return i + i / EPT; }
+
 // LDS scalars used by thread 0 for the Givens recurrence.
 struct GmresScalars {
     double R[SLM_KMAX][SLM_KMAX];   // R[col][row]
-    double cs[SLM_KMAX], sn[SLM_KMAX], g[SLM_KMAX + 1], z[SLM_KMAX], hc[SLM_KMAX + 1];
+    double cs[SLM_KMAX], sn[SLM_KMAX], g[SLM_KMAX + 1], z[SLM_KMAX];
     int flag;
 };
 
@@ -189,100 +196,142 @@ struct Gmres1D {
     int k;
 
     // One Arnoldi step JJ.  Returns true when the iteration stops before
-    // step JJ is taken.
+    // step JJ is taken.  xp: padded exchange buffer; sgp: sigma, padded.
     template <int JJ>
-    __device__ __forceinline__ bool step(const double *__restrict__ sg, T *xb, double *red, int &rb,
+    __device__ __forceinline__ bool step(const double *sgp, T *xp, double *red, int &rb,
                                           GmresScalars *gs, int kmax, double rtol, double beta, int nx)
     {
-        const int tid = threadIdx.x, B = blockDim.x;
+        int tid = threadIdx.x;
+        // Opaque per step: addresses derived from tid are recomputed in every
+        // Arnoldi step instead of being hoisted and held across all of them.
+        __asm__ volatile("" : "+v"(tid));
         if (JJ >= kmax) return true;
+        const int i0 = tid * EPT;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            if (i < nx) xb[i] = V[JJ][e];
-        }
+        for (int e = 0; e < EPT; ++e)
+            if (i0 + e < nx) xp[pidx<EPT>(i0 + e)] = V[JJ][e];
         __syncthreads();
         if (JJ > 0 && gs->flag) return true;
-        // w = V_JJ - sigma .* (D_{p+1} V_JJ)
+        // w = V_JJ - sigma .* (D_{p+1} V_JJ) over the window i0-q .. i0+EPT-1+q
         constexpr int q = DTaps<P>::q;
+        T win[EPT + 2 * q];
+#pragma unroll
+        for (int t = 0; t < q; ++t) {
+            int il = i0 - q + t;
+            il += il < 0 ? nx : 0;
+            int ir = i0 + EPT + t;
+            ir -= ir >= nx ? nx : 0;             // periodic (ragged tails wrap too)
+            win[t] = i0 < nx ? xp[pidx<EPT>(il)] : T(0);
+            win[EPT + q + t] = i0 < nx ? xp[pidx<EPT>(ir)] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) win[q + e] = V[JJ][e];
+        // ragged tail: neighbours past nx wrap to the start of the slice
+        if (i0 + EPT > nx) {
+#pragma unroll
+            for (int e = 0; e < EPT + q; ++e) {
+                const int i = i0 + e;
+                if (i >= nx && i - nx < nx) win[q + e] = xp[pidx<EPT>(i - nx)];
+            }
+        }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            double dv = 0.0;
-            if (i < nx) {
+            if (i0 + e < nx) {
+                double dv = 0.0;
 #pragma unroll
-                for (int t = -q; t <= q; ++t) {
-                    int idx = i + t;
-                    idx += idx < 0 ? nx : 0;
-                    idx -= idx >= nx ? nx : 0;
-                    dv += DTaps<P>::t[t + q] * double(xb[idx]);
-                }
-                w[e] = T(double(V[JJ][e]) - sg[i] * dv);
+                for (int t = 0; t <= 2 * q; ++t) dv += DTaps<P>::t[t] * double(win[e + t]);
+                w[e] = T(double(V[JJ][e]) - sgp[pidx<EPT>(i0 + e)] * dv);
             } else {
                 w[e] = T(0);
             }
         }
-        // classical Gram-Schmidt, twice; the Hessenberg column accumulates
-        // in LDS (thread 0), inner products are wave-uniform
+        // classical Gram-Schmidt, twice; inner products are wave-uniform.
+        // The second pass also reduces ||w||^2, so ||w - V h2||^2 follows
+        // from Pythagoras (V orthonormal); an explicit reduction is used
+        // instead when that difference would cancel badly.
+        double h1[JJ + 1];
 #pragma unroll
-        for (int pass = 0; pass < 2; ++pass) {
-            double h[JJ + 1];
+        for (int i = 0; i <= JJ; ++i) {
+            double s = 0.0;
 #pragma unroll
-            for (int i = 0; i <= JJ; ++i) {
-                double s = 0.0;
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) s += double(V[i][e]) * double(w[e]);
-                h[i] = s;
-            }
-            block_sum_u<JJ + 1>(h, red, rb);
-            rb ^= 1;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                double t = double(w[e]);
-#pragma unroll
-                for (int i = 0; i <= JJ; ++i) t -= h[i] * double(V[i][e]);
-                w[e] = T(t);
-            }
-            if (tid == 0) {
-#pragma unroll
-                for (int i = 0; i <= JJ; ++i) gs->hc[i] = pass ? gs->hc[i] + h[i] : h[i];
-            }
+            for (int e = 0; e < EPT; ++e) s += double(V[i][e] * w[e]);   // FP32 bulk: product in T
+            h1[i] = s;
         }
-        double nn[1] = {0.0};
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) nn[0] += double(w[e]) * double(w[e]);
-        block_sum_u<1>(nn, red, rb);
+        block_sum_u<JJ + 1>(h1, red, rb);
         rb ^= 1;
-        const double hn = sqrt(nn[0]);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            T t = w[e];
+#pragma unroll
+            for (int i = 0; i <= JJ; ++i) t -= T(h1[i]) * V[i][e];
+            w[e] = t;
+        }
+        double h2[JJ + 2];
+#pragma unroll
+        for (int i = 0; i <= JJ; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) s += double(V[i][e] * w[e]);
+            h2[i] = s;
+        }
+        h2[JJ + 1] = 0.0;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) h2[JJ + 1] += double(w[e] * w[e]);
+        block_sum_u<JJ + 2>(h2, red, rb);
+        rb ^= 1;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            T t = w[e];
+#pragma unroll
+            for (int i = 0; i <= JJ; ++i) t -= T(h2[i]) * V[i][e];
+            w[e] = t;
+        }
+        double hh = 0.0;
+#pragma unroll
+        for (int i = 0; i <= JJ; ++i) hh += h2[i] * h2[i];
+        double hn2 = h2[JJ + 1] - hh;
+        if (!(hh <= 0.5 * h2[JJ + 1])) {           // uniform branch
+            double nn[1] = {0.0};
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) nn[0] += double(w[e] * w[e]);
+            block_sum_u<1>(nn, red, rb);
+            rb ^= 1;
+            hn2 = nn[0];
+        }
+        const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
         if (tid == 0) {
-            double *hc = gs->hc;
+            double hc[JJ + 1];
+#pragma unroll
+            for (int i = 0; i <= JJ; ++i) hc[i] = h1[i] + h2[i];
 #pragma unroll
             for (int i = 0; i < JJ; ++i) {          // previous rotations
-                const double t0 = gs->cs[i] * hc[i] + gs->sn[i] * hc[i + 1];
-                const double t1 = -gs->sn[i] * hc[i] + gs->cs[i] * hc[i + 1];
+                const double ci = gs->cs[i], si = gs->sn[i];
+                const double t0 = ci * hc[i] + si * hc[i + 1];
+                const double t1 = -si * hc[i] + ci * hc[i + 1];
                 hc[i] = t0;
                 hc[i + 1] = t1;
             }
             const double den = sqrt(hc[JJ] * hc[JJ] + hn * hn);
-            const double c = hc[JJ] / den, s = hn / den;
+            const double c = hc[JJ] / den, sv = hn / den;
             gs->cs[JJ] = c;
-            gs->sn[JJ] = s;
+            gs->sn[JJ] = sv;
             hc[JJ] = den;
-            gs->g[JJ + 1] = -s * gs->g[JJ];
-            gs->g[JJ] = c * gs->g[JJ];
+            const double gj = gs->g[JJ];
+            gs->g[JJ + 1] = -sv * gj;
+            gs->g[JJ] = c * gj;
 #pragma unroll
             for (int i = 0; i <= JJ; ++i) gs->R[JJ][i] = hc[i];
-            gs->flag = (hn == 0.0) || (fabs(gs->g[JJ + 1]) <= rtol * beta);
+            gs->flag = (hn == 0.0) || (fabs(sv * gj) <= rtol * beta);
         }
         k = JJ + 1;
         const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) V[JJ + 1][e] = T(double(w[e]) * inv);
+        for (int e = 0; e < EPT; ++e) V[JJ + 1][e] = w[e] * T(inv);
         return false;
     }
 
-    // Solve [I - diag(sg) D_{p+1}] y = x in place.  Returns iterations.
-    __device__ __forceinline__ int solve(T (&x)[EPT], const double *__restrict__ sg, T *xb, double *red, int &rb,
+    // Solve [I - diag(sigma) D_{p+1}] y = x in place.  Returns iterations.
+    __device__ __forceinline__ int solve(T (&x)[EPT], const double *sgp, T *xp, double *red, int &rb,
                                          GmresScalars *gs, int kmax, double rtol, int nx)
     {
         const int tid = threadIdx.x;
@@ -305,11 +354,11 @@ struct Gmres1D {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) V[0][e] = T(double(x[e]) / beta);
         k = 0;
-        step<0>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) || step<1>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<2>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) || step<3>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<4>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) || step<5>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<6>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) || step<7>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<8>(sg, xb, red, rb, gs, kmax, rtol, beta, nx) || step<9>(sg, xb, red, rb, gs, kmax, rtol, beta, nx);
+        step<0>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<1>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
+            step<2>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<3>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
+            step<4>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<5>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
+            step<6>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<7>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
+            step<8>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<9>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx);
         // back substitution R z = g (thread 0), then y = V z
         if (tid == 0) {
             for (int i = k - 1; i >= 0; --i) {
@@ -319,35 +368,73 @@ struct Gmres1D {
             }
         }
         __syncthreads();
+        double y[EPT];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            double y = 0.0;
+        for (int e = 0; e < EPT; ++e) y[e] = 0.0;
 #pragma unroll
-            for (int i = 0; i < SLM_KMAX; ++i)
-                if (i < k) y += gs->z[i] * double(V[i][e]);
-            x[e] = T(y);
-        }
+        for (int i = 0; i < SLM_KMAX; ++i)
+            if (i < k) {
+                const double zi = gs->z[i];
+#pragma unroll
+                for (int e = 0; e < EPT; ++e) y[e] += zi * double(V[i][e]);
+            }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) x[e] = T(y[e]);
         return k;
     }
 };
+
+// LDS layout of the coarse kernel: slice (natural order) aliased with the
+// padded exchange buffer (the slice is dead while GMRES runs) | sigma
+// (padded) | reduction scratch | Givens scalars.
+template <typename T, int EPT>
+__host__ __device__ inline size_t coarse_lds_parts(int nx, size_t *o_sg, size_t *o_red, size_t *o_gs)
+{
+    auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
+    const size_t np = (size_t)nx + nx / EPT + 1;
+    size_t o = al(np * sizeof(T));
+    *o_sg = o;
+    o = al(o + np * sizeof(double));
+    *o_red = o;
+    o = al(o + SLM_RED_DOUBLES * sizeof(double));
+    *o_gs = o;
+    return o + sizeof(GmresScalars);
+}
 
 template <typename T, int P, int EPT>
 __global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, B = blockDim.x, nx = a.nx;
+    const int tid = threadIdx.x, nx = a.nx, j = blockIdx.x;
     const long long S = a.S;
+    size_t osg, ored, ogs;
+    coarse_lds_parts<T, EPT>(nx, &osg, &ored, &ogs);
     T *sl = reinterpret_cast<T *>(smem);
-    const size_t off = ((size_t)nx * sizeof(T) + 15) & ~size_t(15);
-    double *red = reinterpret_cast<double *>(smem + off);
-    GmresScalars *gs = reinterpret_cast<GmresScalars *>(red + SLM_RED_DOUBLES);
+    T *xp = sl;
+    double *sgp = reinterpret_cast<double *>(smem + osg);
+    double *red = reinterpret_cast<double *>(smem + ored);
+    GmresScalars *gs = reinterpret_cast<GmresScalars *>(smem + ogs);
     const double *disp = static_cast<const double *>(a.disp);
+    const T *Cin = static_cast<const T *>(a.Cin);
     const T *G = static_cast<const T *>(a.G);
     T *Vout = static_cast<T *>(a.Vout);
-    const long long n_first = a.n_base + (long long)blockIdx.x * a.stride_chain;
+    T *Cout = static_cast<T *>(a.Cout);
+    const long long n_first = a.n_base + (long long)j * a.stride_chain;
+    const int i0 = tid * EPT;
 
     T val[EPT];
-    chain_start<T, EPT>(a, sl, val, n_first);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = i0 + e;
+        T s = T(0);
+        if (i < nx) {
+            if (Cin) s = Cin[(long long)j * a.cin_stride + i];
+            sl[i] = s;
+            if (Vout && a.write_start) Vout[n_first * S + i] = s;
+            if (Cout && j == 0 && a.cout_shift) Cout[i] = s;
+        }
+        val[e] = s;
+    }
     __syncthreads();
     int rb = 0;
     Gmres1D<T, P, EPT> gm;
@@ -356,16 +443,17 @@ __global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
         const long long n = n_first + k;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
+            const int i = i0 + e;
+            if (i < nx) sgp[pidx<EPT>(i)] = a.sigma[n * S + i];
             val[e] = i < nx ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
         }
-        __syncthreads();                         // every read of the slice is done
-        niter += gm.solve(val, a.sigma + n * S, sl, red, rb, gs, a.kmax, a.rtol, nx);
+        __syncthreads();                         // every read of the slice is done, sigma staged
+        niter += gm.solve(val, sgp, xp, red, rb, gs, a.kmax, a.rtol, nx);
         ++nsolve;
         const bool wv = Vout && (k + 1 < a.nsteps || a.write_last);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
+            const int i = i0 + e;
             if (i < nx) {
                 if (G) val[e] += G[(n + 1) * S + i];
                 sl[i] = val[e];
@@ -374,7 +462,27 @@ __global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
         }
         __syncthreads();
     }
-    chain_finish<T, EPT>(a, val, red, rb);
+    if (Cout) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            if (i0 + e < nx) Cout[(long long)(j + a.cout_shift) * S + i0 + e] = val[e];
+    }
+    if (a.R) {
+        const T *Cref = static_cast<const T *>(a.Cref);
+        T *R = static_cast<T *>(a.R);
+        double acc[1] = {0.0};
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = i0 + e;
+            if (i < nx) {
+                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
+                R[(long long)(j + 1) * S + i] = r;
+                acc[0] += double(r) * double(r);
+            }
+        }
+        block_sum<1>(acc, red, rb);
+        if (tid == 0) a.partial[j] = acc[0];
+    }
     if (tid == 0 && a.counter) {
         atomicAdd(a.counter, nsolve);
         atomicAdd(a.counter + 1, niter);
@@ -440,22 +548,25 @@ hipError_t fine_p(const ChainArgs &a, int nchains, hipStream_t st)
     }
 }
 
+template <typename T, int P, int EPT>
+hipError_t coarse_launch(const ChainArgs &a, int nchains, hipStream_t st)
+{
+    size_t o1, o2, o3;
+    const size_t lds = coarse_lds_parts<T, EPT>(a.nx, &o1, &o2, &o3);
+    const int block = ((a.nx + EPT - 1) / EPT + 63) / 64 * 64;
+    return launch(coarse1d<T, P, EPT>, nchains, block, lds, a, st);
+}
+
+// Elements per thread: the smallest power of two that keeps the workgroup at
+// or below COARSE_MAXB threads.
 template <typename T, int P>
 hipError_t coarse_ept(const ChainArgs &a, int nchains, hipStream_t st)
 {
-    const int block = a.nx >= COARSE_MAXB ? COARSE_MAXB : ((a.nx + 63) / 64) * 64;
-    const int ept = (a.nx + block - 1) / block;
-    const size_t lds = (((size_t)a.nx * sizeof(T) + 15) & ~size_t(15)) + SLM_RED_DOUBLES * sizeof(double) +
-                       sizeof(GmresScalars);
-    switch (ept) {
-    case 1: return launch(coarse1d<T, P, 1>, nchains, block, lds, a, st);
-    case 2: return launch(coarse1d<T, P, 2>, nchains, block, lds, a, st);
-    case 3:
-    case 4: return launch(coarse1d<T, P, 4>, nchains, block, lds, a, st);
-    case 5: case 6: case 7:
-    case 8: return launch(coarse1d<T, P, 8>, nchains, block, lds, a, st);
-    default: return launch(coarse1d<T, P, 16>, nchains, block, lds, a, st);
-    }
+    if (a.nx <= COARSE_MAXB) return coarse_launch<T, P, 1>(a, nchains, st);
+    if (a.nx <= 2 * COARSE_MAXB) return coarse_launch<T, P, 2>(a, nchains, st);
+    if (a.nx <= 4 * COARSE_MAXB) return coarse_launch<T, P, 4>(a, nchains, st);
+    if (a.nx <= 8 * COARSE_MAXB) return coarse_launch<T, P, 8>(a, nchains, st);
+    return coarse_launch<T, P, 16>(a, nchains, st);
 }
 
 template <typename T>

@@ -177,7 +177,10 @@ def test_mgrit_solve(name, oracle, torch, built):
     assert st["n_levels"] == st_ref["n_levels"]
     if plan.L > 1:
         assert np.abs(hist - h_ref).max() <= 1e-8 * h_ref[0] + 1e-12 * np.abs(h_ref).max()
-        big = h_ref > 1e-12 * h_ref[0]
+        # relative agreement where rho_k is far above its rounding floor
+        # (~1e-16 * ||u|| * sqrt(#entries)); deeper entries are covered by
+        # the absolute bound above
+        big = h_ref > 1e-7 * h_ref[0]
         assert np.abs(hist[big] / h_ref[big] - 1).max() < 1e-6
         assert st["gmres_solves"] == st_ref["gmres_solves"]
         # C-points that are already exact leave residuals of pure rounding
