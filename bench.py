@@ -42,7 +42,46 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk variant")
     ap.add_argument("--cpu-nt", type=int, default=1024, help="time steps of the CPU oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="run only the level-0 F+C sweep kernel and a 1 GiB device copy (for counter runs)")
     return ap.parse_args()
+
+
+def kernel_only(args):
+    """The dominant HBM kernel alone, plus a plain copy of known size whose
+    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    from paper_2203_13382_amd import Plan
+    from paper_2203_13382_amd import inputs as I
+    from paper_2203_13382_amd import workloads as W
+    pr, sv, _ = W.config(2)
+    plan = Plan(pr, sv, "fp64").setup()
+    ui = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 1)).cuda()
+    cin = ui[::sv.m[0]].contiguous()
+    cout = torch.empty_like(cin)
+    ms = timed(torch, lambda: plan.relax_into(0, "FC", c_in=cin, c_out=cout), args.kernel_reps)
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
+    dst = torch.empty_like(src)
+    cms = timed(torch, lambda: dst.copy_(src), 3)
+    nc = pr.nt // sv.m[0]
+    print(json.dumps({"kernel": "fine1d level-0 FC sweep", "launch_ms": ms,
+                      "bytes_per_launch": 8 * pr.S * (pr.nt + 2 * nc + 1),
+                      "copy_bytes_each_way": src.numel() * 8, "copy_ms": cms}))
+
+
+def measured_traffic():
+    """HBM bytes per launch of the level-0 sweep from the committed counter
+    summary, or None once the kernel source differs from the one profiled."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "cfg2_kernels.md")
+    src = os.path.join(ROOT, "paper_2203_13382_amd", "csrc", "slm_chain1d.hip")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
+                  and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        return int(kv["traffic_bytes_per_launch"]) if kv.get("kernel_source_sha256_16", "").strip() == sha else None
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def timed(torch, fn, reps, warm=1):
@@ -89,6 +128,8 @@ def main():
     from paper_2203_13382_amd import inputs as I
     from paper_2203_13382_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.kernel_only:
+        return kernel_only(args)
     dev = torch.device("cuda")
 
     pr, sv, _ = W.config(2)
@@ -163,7 +204,7 @@ def main():
         "speedup_vs_seq": (trace_ms + seq_ms) / ms,
         "roofline": {"kernel": "level-0 F+C relaxation sweep (chain1d, FP64)", "bound": "hbm",
                      "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": k_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "launch_ms": k_ms, "bytes_per_launch": k_bytes},
+                     "traffic": measured_traffic(), "launch_ms": k_ms, "bytes_per_launch": k_bytes},
     }
 
     # ---------------------------------------------------------------- FP32 bulk
