@@ -1,0 +1,468 @@
+// slm_chain2d.hip -- relaxation sweeps on a periodic 2D mesh.
+//
+// A 2D slice (nx*nx values) does not fit in one CU's LDS, so a sweep over m
+// level steps is a sequence of launches, one per step index, each advancing
+// every coarse interval ("chain") of the sweep at once: the grid spans the
+// points of a slice times the chains.  Slices in flight live in a
+// ping-pong work buffer in HBM.
+//
+// Level 0 applies the tensor-product semi-Lagrangian step (Sec. 4.1).
+// Coarse levels apply eq. (BEOper_2D) with the multilevel sigma of Sec. 4.3:
+//     v <- [I - diag(sx) D_x - diag(sy) D_y]^{-1} S_{p,r*} v,
+// D_x = I (x) D_{p+1}, D_y = D_{p+1} (x) I.  The inverse is applied by GMRES
+// (zero guess, classical Gram-Schmidt twice, Givens, exit at rtol or kmax),
+// batched over the chains: every Arnoldi phase is one launch over all
+// systems, inner products are per-block FP64 partial sums reduced in a fixed
+// order, and a one-thread-per-system kernel runs the Givens recurrence.
+// Converged systems skip their work through a per-system flag.
+#include "slm_internal.h"
+
+namespace {
+
+constexpr int TPB = 256;            // threads per block of the point kernels
+constexpr int NPART = 16;           // partial-sum slots per block
+
+// ------------------------------------------------------------ interpolation
+template <int P, typename T, typename TD>
+__device__ __forceinline__ T interp2(const T *__restrict__ s, int i, int j, TD dx, TD dy, int nx)
+{
+    const TD fx = floor(dx), fy = floor(dy);
+    const T ex = T(dx - fx), ey = T(dy - fy);
+    const int firstx = stencil_first<T>(P, ex), firsty = stencil_first<T>(P, ey);
+    const int bx = wrap_mod(i - int(fx) + firstx, nx);
+    const int by = wrap_mod(j - int(fy) + firsty, nx);
+    T wx[P + 1], wy[P + 1];
+    lagrange_weights<P, T>(-ex - T(firstx), wx);
+    lagrange_weights<P, T>(-ey - T(firsty), wy);
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+        int row = by + b;
+        row -= row >= nx ? nx : 0;
+        const T *sr = s + (long long)row * nx;
+        T ar = T(0);
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            int col = bx + a;
+            col -= col >= nx ? nx : 0;
+            ar += wx[a] * sr[col];
+        }
+        acc += wy[b] * ar;
+    }
+    return acc;
+}
+
+// One level step for every chain c: dst[c] = S(n_c) src[c] (+ G[n_c+1]).
+// n_c = n_first + c*stride.  src may be null (zero start).
+template <typename T, typename TD, int P>
+__global__ void __launch_bounds__(TPB) step2d_kernel(const T *__restrict__ src, long long src_stride,
+                                                     T *__restrict__ dst, long long dst_stride,
+                                                     const TD *__restrict__ disp, long long plane, int nx,
+                                                     long long n_first, int stride, const T *__restrict__ G,
+                                                     T *__restrict__ Vout)
+{
+    const long long S = (long long)nx * nx;
+    const int c = blockIdx.y;
+    const long long n = n_first + (long long)c * stride;
+    const T *s = src ? src + c * src_stride : nullptr;
+    T *d = dst + c * dst_stride;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        const int i = (int)(id % nx), j = (int)(id / nx);
+        T v = s ? interp2<P, T, TD>(s, i, j, disp[n * S + id], disp[plane + n * S + id], nx) : T(0);
+        if (G) v += G[(n + 1) * S + id];
+        d[id] = v;
+        if (Vout) Vout[(n + 1) * S + id] = v;
+    }
+}
+
+// Chain epilogue: Cout[c+shift] = last[c]; or residual R[c+1] = last[c] - Cref[c+1]
+// with per-(chain, block) partial sums of squares.
+template <typename T>
+__global__ void __launch_bounds__(TPB) finish2d_kernel(const T *__restrict__ last, long long S, T *Cout, int shift,
+                                                       const T *__restrict__ Cref, T *R, double *partial)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.y;
+    double acc[1] = {0.0};
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        const T v = last[c * S + id];
+        if (Cout) Cout[(c + shift) * S + id] = v;
+        if (R) {
+            const T r = Cref ? T(v - Cref[(c + 1) * S + id]) : v;
+            R[(c + 1) * S + id] = r;
+            acc[0] += double(r) * double(r);
+        }
+    }
+    if (R) {
+        block_sum<1>(acc, red, 0);
+        if (threadIdx.x == 0) partial[(long long)c * gridDim.x + blockIdx.x] = acc[0];
+    }
+}
+
+// Start slices: dst[c] = src[c*stride] or 0; optional Vout[n_first(c)] and Cout[0].
+template <typename T>
+__global__ void __launch_bounds__(TPB) start2d_kernel(const T *__restrict__ Cin, long long cin_stride, T *dst,
+                                                      long long S, T *Vout, long long n_first, int stride,
+                                                      T *Cout0)
+{
+    const int c = blockIdx.y;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        const T v = Cin ? Cin[c * cin_stride + id] : T(0);
+        dst[c * S + id] = v;
+        if (Vout) Vout[(n_first + (long long)c * stride) * S + id] = v;
+        if (Cout0 && c == 0) Cout0[id] = v;
+    }
+}
+
+// ------------------------------------------------------------ batched GMRES
+// (per-system Givens state Gs2 is declared in slm_internal.h)
+
+// Fixed-order sum of the nb block partials of slot q for system c.
+__device__ __forceinline__ double part_sum(const double *part, int c, int nb, int q)
+{
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[((long long)c * nb + b) * NPART + q];
+    return s;
+}
+
+template <int NV>
+__device__ __forceinline__ void write_parts(double (&v)[NV], double *red, double *part, int c)
+{
+    block_sum<NV>(v, red, 0);
+    if (threadIdx.x < NV) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = v[threadIdx.x];
+}
+
+// partials of b.b
+template <typename T>
+__global__ void __launch_bounds__(TPB) g2_norm0(const T *__restrict__ b, long long S, double *part)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.y;
+    double v[1] = {0.0};
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        const double x = b[c * S + id];
+        v[0] += x * x;
+    }
+    write_parts<1>(v, red, part, c);
+}
+
+// beta, V0 = b / beta (every block recomputes beta from the partials)
+template <typename T>
+__global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long long S, const double *part, int nb,
+                                                 T *V, Gs2 *gs, int kmax)
+{
+    const int c = blockIdx.y;
+    const double beta = sqrt(part_sum(part, c, nb, 0));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Gs2 &g = gs[c];
+        g.beta = beta;
+        g.k = 0;
+        g.done = (beta == 0.0 || kmax <= 0) ? 1 : 0;
+        g.g[0] = beta;
+        for (int i = 1; i <= SLM_KMAX; ++i) g.g[i] = 0.0;
+    }
+    if (beta == 0.0) return;
+    const double inv = 1.0 / beta;
+    T *V0 = V + (long long)c * (SLM_KMAX + 1) * S;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB)
+        V0[id] = T(double(b[c * S + id]) * inv);
+}
+
+// w = V_j - sx .* (D_x V_j) - sy .* (D_y V_j); partials of V_i . w, i <= j.
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__restrict__ W, long long S, int nx,
+                                                  const double *__restrict__ sig, long long plane, long long n_first,
+                                                  int stride, int j, const Gs2 *gs, double *part)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.y;
+    if (gs[c].done) return;
+    const long long n = n_first + (long long)c * stride;
+    const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
+    const T *vj = Vc + (long long)j * S;
+    const double *sx = sig + n * S, *sy = sig + plane + n * S;
+    constexpr int q = DTaps<P>::q;
+    double h[SLM_KMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        const int i = (int)(id % nx), jr = (int)(id / nx);
+        double dxv = 0.0, dyv = 0.0;
+#pragma unroll
+        for (int t = -q; t <= q; ++t) {
+            int ii = i + t, jj = jr + t;
+            ii += ii < 0 ? nx : 0;
+            ii -= ii >= nx ? nx : 0;
+            jj += jj < 0 ? nx : 0;
+            jj -= jj >= nx ? nx : 0;
+            dxv += DTaps<P>::t[t + q] * double(vj[(long long)jr * nx + ii]);
+            dyv += DTaps<P>::t[t + q] * double(vj[(long long)jj * nx + i]);
+        }
+        const T w = T(double(vj[id]) - sx[id] * dxv - sy[id] * dyv);
+        W[c * S + id] = w;
+#pragma unroll
+        for (int k = 0; k <= SLM_KMAX; ++k)
+            if (k <= j) h[k] += double(Vc[(long long)k * S + id]) * double(w);
+    }
+    block_sum<SLM_KMAX + 1>(h, red, 0);
+    if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+}
+
+// w -= sum_i h_i V_i with h from the partials; then partials of V_i . w (i <= j)
+// when `dots`, or of w . w otherwise.  The h of pass 1 are kept in hkeep.
+template <typename T>
+__global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__restrict__ W, long long S, int j,
+                                                  const Gs2 *gs, const double *part_in, double *part_out, int dots,
+                                                  double *hkeep)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    __shared__ double hs[SLM_KMAX + 1];
+    const int c = blockIdx.y;
+    if (gs[c].done) return;
+    const int nb = gridDim.x;
+    if (threadIdx.x <= j) {
+        const double hv = part_sum(part_in, c, nb, threadIdx.x);
+        hs[threadIdx.x] = hv;
+        if (hkeep && blockIdx.x == 0) hkeep[c * (SLM_KMAX + 1) + threadIdx.x] = hv;
+    }
+    __syncthreads();
+    const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
+    double h[SLM_KMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        double t = double(W[c * S + id]);
+        for (int k = 0; k <= j; ++k) t -= hs[k] * double(Vc[(long long)k * S + id]);
+        const T w = T(t);
+        W[c * S + id] = w;
+        if (dots) {
+#pragma unroll
+            for (int k = 0; k <= SLM_KMAX; ++k)
+                if (k <= j) h[k] += double(Vc[(long long)k * S + id]) * double(w);
+        } else {
+            h[0] += double(w) * double(w);
+        }
+    }
+    block_sum<SLM_KMAX + 1>(h, red, 0);
+    const int nv = dots ? j + 1 : 1;
+    if (threadIdx.x < nv) part_out[((long long)c * nb + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+}
+
+// Givens recurrence, one thread per system.  h = hkeep (pass 1) + pass-2
+// coefficients, hn from the norm partials (Sec. 3.3 GMRES, same arithmetic
+// order as the 1D kernel).
+__global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *hkeep, const double *part2,
+                          const double *partn, int nb, double rtol, int kmax)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nsys) return;
+    Gs2 &g = gs[c];
+    if (g.done) return;
+    double hc[SLM_KMAX + 1];
+    for (int i = 0; i <= j; ++i) hc[i] = hkeep[c * (SLM_KMAX + 1) + i] + part_sum(part2, c, nb, i);
+    const double hn = sqrt(part_sum(partn, c, nb, 0));
+    for (int i = 0; i < j; ++i) {
+        const double t0 = g.cs[i] * hc[i] + g.sn[i] * hc[i + 1];
+        const double t1 = -g.sn[i] * hc[i] + g.cs[i] * hc[i + 1];
+        hc[i] = t0;
+        hc[i + 1] = t1;
+    }
+    const double den = sqrt(hc[j] * hc[j] + hn * hn);
+    const double cc = hc[j] / den, ss = hn / den;
+    g.cs[j] = cc;
+    g.sn[j] = ss;
+    hc[j] = den;
+    const double gj = g.g[j];
+    g.g[j + 1] = -ss * gj;
+    g.g[j] = cc * gj;
+    for (int i = 0; i <= j; ++i) g.R[j][i] = hc[i];
+    g.hn[j] = hn;
+    g.k = j + 1;
+    if (hn == 0.0 || fabs(ss * gj) <= rtol * g.beta || j + 1 >= kmax) g.done = 1;
+}
+
+// V_{j+1} = w / hn for systems still iterating.
+template <typename T>
+__global__ void __launch_bounds__(TPB) g2_normalize(T *V, const T *__restrict__ W, long long S, int j, const Gs2 *gs)
+{
+    const int c = blockIdx.y;
+    if (gs[c].done) return;
+    const double hn = gs[c].hn[j];
+    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    T *vn = V + ((long long)c * (SLM_KMAX + 1) + j + 1) * S;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB)
+        vn[id] = T(double(W[c * S + id]) * inv);
+}
+
+// y = V z (back substitution per block), then dst[c] = y (+ G[n+1]), Vout.
+template <typename T>
+__global__ void __launch_bounds__(TPB) g2_combine(const T *__restrict__ V, long long S, const Gs2 *gs, T *dst,
+                                                   long long dst_stride, long long n_first, int stride,
+                                                   const T *__restrict__ G, T *Vout)
+{
+    __shared__ double z[SLM_KMAX];
+    const int c = blockIdx.y;
+    const Gs2 &g = gs[c];
+    const int k = g.k;
+    if (threadIdx.x == 0) {
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g.g[i];
+            for (int t = i + 1; t < k; ++t) s -= g.R[t][i] * z[t];
+            z[i] = s / g.R[i][i];
+        }
+    }
+    __syncthreads();
+    const long long n = n_first + (long long)c * stride;
+    const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        double y = 0.0;
+        for (int i = 0; i < k; ++i) y += z[i] * double(Vc[(long long)i * S + id]);
+        T v = T(y);
+        if (G) v += G[(n + 1) * S + id];
+        dst[c * dst_stride + id] = v;
+        if (Vout) Vout[(n + 1) * S + id] = v;
+    }
+}
+
+__global__ void g2_count(const Gs2 *gs, int nsys, unsigned long long *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        unsigned long long it = 0;
+        for (int c = 0; c < nsys; ++c) it += gs[c].k;
+        counter[0] += nsys;
+        counter[1] += it;
+    }
+}
+
+// ------------------------------------------------------------ host side
+int nblocks(long long S)
+{
+    long long b = (S + TPB - 1) / TPB;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+template <typename T, typename TD>
+hipError_t launch_step(int p, dim3 grid, hipStream_t st, const T *src, long long ss, T *dst, long long ds,
+                       const TD *disp, long long plane, int nx, long long n_first, int stride, const T *G, T *Vout)
+{
+#define STEP2D(PP) hipLaunchKernelGGL((step2d_kernel<T, TD, PP>), grid, dim3(TPB), 0, st, src, ss, dst, ds, disp, \
+                                      plane, nx, n_first, stride, G, Vout)
+    switch (p) {
+    case 1: STEP2D(1); break;
+    case 2: STEP2D(2); break;
+    case 3: STEP2D(3); break;
+    case 4: STEP2D(4); break;
+    default: STEP2D(5); break;
+    }
+#undef STEP2D
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, const T *V, T *W, long long S, int nx, const double *sig,
+                         long long plane, long long n_first, int stride, int j, const Gs2 *gs, double *part)
+{
+    switch (p) {
+    case 1: hipLaunchKernelGGL((g2_matvec<T, 1>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, j, gs, part); break;
+    case 3: hipLaunchKernelGGL((g2_matvec<T, 3>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, j, gs, part); break;
+    case 5: hipLaunchKernelGGL((g2_matvec<T, 5>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, j, gs, part); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// One batch of chains [c0, c0+nch) of a sweep, all in the same level.
+template <typename T>
+hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0, int nch, hipStream_t st)
+{
+    using TD0 = T;   // level-0 displacement type follows the bulk type
+    const long long S = a.S;
+    const int nx = a.nx;
+    const LevelInfo &L = P.lv[level];
+    const long long plane = (long long)L.N * S;
+    T *Wb = (T *)ws_at(P, P.w2);
+    T *bufs[2] = {Wb, Wb + (long long)P.cap2 * S};
+    const int nb = nblocks(S);
+    dim3 grid(nb, nch);
+    const long long n_first0 = a.n_base + (long long)c0 * a.stride_chain;
+    const T *Cin = a.Cin ? (const T *)a.Cin + (long long)c0 * a.cin_stride : nullptr;
+    T *Vout = (T *)a.Vout;
+    T *Cout = (T *)a.Cout;
+    hipError_t e;
+    // start slices
+    hipLaunchKernelGGL(start2d_kernel<T>, grid, dim3(TPB), 0, st, Cin, a.cin_stride, bufs[0], S,
+                       a.write_start ? Vout : nullptr, n_first0, a.stride_chain,
+                       (Cout && a.cout_shift && c0 == 0) ? Cout : nullptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int cur = 0;
+    for (int k = 0; k < a.nsteps; ++k) {
+        const bool last = k + 1 == a.nsteps;
+        T *vo = (Vout && (!last || a.write_last)) ? Vout : nullptr;
+        if (level == 0) {
+            if (P.d.precision == SLM_FP32_BULK)
+                e = launch_step<T, float>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S,
+                                          (const float *)ws_at(P, L.disp), plane, nx, n_first0 + k, a.stride_chain,
+                                          (const T *)a.G, vo);
+            else
+                e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S,
+                                           (const double *)ws_at(P, L.disp), plane, nx, n_first0 + k,
+                                           a.stride_chain, (const T *)a.G, vo);
+            if (e != hipSuccess) return e;
+        } else {
+            // interpolation into the GMRES right-hand side
+            T *bb = (T *)ws_at(P, P.g2b);
+            e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bb, S, (const double *)ws_at(P, L.disp), plane,
+                                       nx, n_first0 + k, a.stride_chain, nullptr, nullptr);
+            if (e != hipSuccess) return e;
+            T *V = (T *)ws_at(P, P.g2v);
+            T *W = (T *)ws_at(P, P.g2w);
+            Gs2 *gs = (Gs2 *)ws_at(P, P.g2s);
+            double *pa = (double *)ws_at(P, P.g2p), *pb = pa + (long long)P.capg * nb * NPART;
+            double *pc = pb + (long long)P.capg * nb * NPART;
+            double *hk = pc + (long long)P.capg * nb * NPART;
+            const double *sig = (const double *)ws_at(P, L.sigma);
+            hipLaunchKernelGGL(g2_norm0<T>, grid, dim3(TPB), 0, st, bb, S, pa);
+            hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, bb, S, pa, nb, V, gs, a.kmax);
+            for (int j = 0; j < a.kmax; ++j) {
+                if ((e = launch_matvec<T>(P.d.p, grid, st, V, W, S, nx, sig, plane, n_first0 + k, a.stride_chain, j, gs,
+                                          pa)) != hipSuccess)
+                    return e;
+                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, pa, pb, 1, hk);
+                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, pb, pc, 0, (double *)nullptr);
+                hipLaunchKernelGGL(g2_givens, dim3((nch + 63) / 64), dim3(64), 0, st, gs, nch, j, hk, pb, pc, nb,
+                                   a.rtol, a.kmax);
+                hipLaunchKernelGGL(g2_normalize<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs);
+            }
+            hipLaunchKernelGGL(g2_combine<T>, grid, dim3(TPB), 0, st, V, S, gs, bufs[cur ^ 1], S, n_first0 + k,
+                               a.stride_chain, (const T *)a.G, vo);
+            if (a.counter) hipLaunchKernelGGL(g2_count, dim3(1), dim3(64), 0, st, gs, nch, a.counter);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        cur ^= 1;
+    }
+    if (Cout || a.R) {
+        double *part = (double *)ws_at(P, P.part2) + (long long)c0 * nb;
+        hipLaunchKernelGGL(finish2d_kernel<T>, grid, dim3(TPB), 0, st, bufs[cur], S,
+                           Cout ? Cout + (long long)c0 * S : nullptr, a.cout_shift,
+                           a.Cref ? (const T *)a.Cref + (long long)c0 * S : nullptr,
+                           a.R ? (T *)a.R + (long long)c0 * S : nullptr, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+int chain2d_blocks(long long S) { return nblocks(S); }
+
+hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
+{
+    const int cap = level > 0 ? P.capg : P.cap2;
+    for (int c0 = 0; c0 < nchains; c0 += cap) {
+        const int nch = nchains - c0 < cap ? nchains - c0 : cap;
+        hipError_t e = P.d.precision == SLM_FP32_BULK ? chain_batch<float>(P, level, a, c0, nch, st)
+                                                      : chain_batch<double>(P, level, a, c0, nch, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}

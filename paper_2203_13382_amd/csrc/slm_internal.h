@@ -19,6 +19,16 @@ struct LevelInfo {
     size_t C = 0;           // [(N/m+1)][S] T: C-point buffer (not on the coarsest level)
 };
 
+// Per-system Givens state of the batched 2D GMRES.
+struct Gs2 {
+    double R[SLM_KMAX][SLM_KMAX];    // R[col][row]
+    double cs[SLM_KMAX], sn[SLM_KMAX], g[SLM_KMAX + 1], hn[SLM_KMAX];
+    double beta;
+    int k;                           // iterations done
+    int done;
+};
+#define SLM_NPART2 16
+
 struct slm_plan {
     slm_desc d;                         // copy; pointers below own the arrays
     std::vector<slm_wave_term> alpha, beta;
@@ -30,6 +40,9 @@ struct slm_plan {
     size_t partial = 0;                 // [max intervals] double
     size_t norm = 0;                    // 1 double
     size_t counter = 0;                 // 2 x uint64: gmres solves, iterations
+    // 2D: chains per launch batch, ping-pong slices and batched-GMRES state
+    int cap2 = 0, capg = 0, nb2 = 0;
+    size_t w2 = 0, g2b = 0, g2v = 0, g2w = 0, g2s = 0, g2p = 0, part2 = 0;
     size_t ws_bytes = 0;
     char *ws = nullptr;
     bool ready = false;
@@ -70,6 +83,7 @@ hipError_t launch_chain_1d(const slm_plan &P, int level, int nchains, const Chai
 hipError_t launch_trace_2d(const slm_plan &P, hipStream_t st);
 hipError_t launch_backtrack_2d(const slm_plan &P, int level, hipStream_t st);
 hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);
+int chain2d_blocks(long long S);
 hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st);
 hipError_t launch_axpy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
                               int count, int S, int elem, int assign, hipStream_t st);

@@ -70,6 +70,13 @@ ChainArgs base_args(const slm_plan &P, int level)
     return a;
 }
 
+// Device sum of the residual partial sums of a sweep over nc chains.
+hipError_t sum_norm(const slm_plan &P, int nc, double *out, hipStream_t st)
+{
+    if (P.d.dim == 2) return launch_sum_partials((const double *)ws_at(P, P.part2), nc * P.nb2, out, st);
+    return launch_sum_partials((const double *)ws_at(P, P.partial), nc, out, st);
+}
+
 hipError_t chain(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
 {
     return P.d.dim == 1 ? launch_chain_1d(P, level, nchains, a, st) : launch_chain_2d(P, level, nchains, a, st);
@@ -247,6 +254,26 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
             if ((size_t)(L.N / L.m) > maxc) maxc = L.N / L.m;
         }
     }
+    if (d->dim == 2) {
+        size_t cap2 = 1, capg = 1;
+        for (int l = 0; l < P->L; ++l) {
+            const size_t nc = P->lv[l].m ? (size_t)P->lv[l].N / P->lv[l].m : 1;
+            if (nc > cap2) cap2 = nc;
+            if (l > 0 && nc > capg) capg = nc;
+        }
+        P->cap2 = (int)cap2;
+        P->capg = (int)capg;
+        P->nb2 = chain2d_blocks((long long)S);
+        P->w2 = take(2 * cap2 * S * el);
+        P->part2 = take(cap2 * (size_t)P->nb2 * sizeof(double));
+        if (P->L > 1) {
+            P->g2b = take(capg * S * el);
+            P->g2v = take(capg * (SLM_KMAX + 1) * S * el);
+            P->g2w = take(capg * S * el);
+            P->g2s = take(capg * sizeof(Gs2));
+            P->g2p = take((3 * capg * (size_t)P->nb2 * SLM_NPART2 + capg * (SLM_KMAX + 1)) * sizeof(double));
+        }
+    }
     P->partial = take(maxc * sizeof(double));
     P->norm = take(sizeof(double));
     P->counter = take(2 * sizeof(unsigned long long));
@@ -358,7 +385,7 @@ int slm_relax(slm_plan *P, int level, int mode, const void *d_g, const void *d_c
     }
     if (mode == SLM_SWEEP_RES && h_norm) {
         double *dn = (double *)ws_at(*P, P->norm);
-        HIPCHK(launch_sum_partials((double *)ws_at(*P, P->partial), nc, dn, st));
+        HIPCHK(sum_norm(*P, nc, dn, st));
         double v = 0.0;
         HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -440,7 +467,7 @@ int slm_solve(slm_plan *P, const void *d_u0, void *d_u, slm_stats *stats, double
                 HIPCHK(chain(*P, 0, nc0, a, st));
                 sv.updates += (long long)P->d.nt * S;
             }
-            HIPCHK(launch_sum_partials((double *)ws_at(*P, P->partial), nc0, dn, st));
+            HIPCHK(sum_norm(*P, nc0, dn, st));
             double v = 0.0;
             HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -491,8 +518,3 @@ int slm_solve(slm_plan *P, const void *d_u0, void *d_u, slm_stats *stats, double
 }
 
 }  // extern "C"
-
-hipError_t launch_chain_2d(const slm_plan &, int, int, const ChainArgs &, hipStream_t)
-{
-    return hipErrorNotSupported;
-}
