@@ -167,6 +167,38 @@ int slm_step(slm_plan *plan, const void *d_u0, void *d_u, int store_all, void *s
 int slm_solve(slm_plan *plan, const void *d_u0, void *d_u, slm_stats *stats,
               double *h_hist, int hist_cap, void *stream);
 
+/* ---- Many independent 1D problems solved together (a batch) --------------
+ * The level-0 relaxation sweeps of every problem run as one persistent
+ * launch over a work list of (problem, coarse interval) items; coarse-level
+ * sweeps are batched per (interpolation order, elements per thread) class;
+ * convergence is decided per problem on the device, so one V-cycle of the
+ * whole batch can be captured once as a HIP graph and replayed until every
+ * problem has stopped.  Every problem keeps the semantics (hierarchy,
+ * stopping test, iteration count) of slm_solve on its own descriptor.
+ * Constraints: dim = 1, odd p, and all descriptors share precision and
+ * relax.  Errors of the slm_batch_* calls are reported by
+ * slm_last_error(NULL).  Calls on one batch must not overlap. */
+typedef struct slm_batch slm_batch;
+int slm_batch_create(const slm_desc *descs, int n, slm_batch **out);
+void slm_batch_destroy(slm_batch *batch);
+int slm_batch_workspace_size(const slm_batch *batch, size_t *bytes);
+/* Binds one caller-owned, 256-byte aligned workspace of at least
+ * slm_batch_workspace_size() bytes for all problems, runs every problem's
+ * setup (departure points, backtracking, sigma) and uploads the batch's
+ * work lists. */
+int slm_batch_setup(slm_batch *batch, void *d_ws, size_t bytes, void *stream);
+/* Autotuner: times the persistent level-0 kernel for a few launch shapes
+ * (workgroups per CU, item order) and keeps the fastest.  With a non-NULL
+ * cache_path the choice is read from / appended to that text file, keyed
+ * by the batch's shapes.  Calls before setup return SLM_ENOTSETUP. */
+int slm_batch_tune(slm_batch *batch, const char *cache_path, void *stream);
+/* Solve every problem: d_u0[i] / d_u[i] as for slm_solve (T of the batch).
+ * stats[i] receives problem i's statistics; h_hist (optional) is
+ * [n][hist_cap].  use_graph != 0 replays one captured V-cycle.  Returns
+ * SLM_OK when every problem converged, else the largest status. */
+int slm_batch_solve(slm_batch *batch, const void *const *d_u0, void *const *d_u, slm_stats *stats,
+                    double *h_hist, int hist_cap, int use_graph, void *stream);
+
 const char *slm_strerror(int code);
 const char *slm_last_error(const slm_plan *plan);   /* plan may be NULL */
 

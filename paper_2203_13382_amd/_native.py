@@ -58,6 +58,13 @@ SIGNATURES = [
     ("slm_relax", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]),
     ("slm_step", C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
     ("slm_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats), C.POINTER(C.c_double), C.c_int, _VP]),
+    ("slm_batch_create", C.c_int, [C.POINTER(Desc), C.c_int, C.POINTER(_VP)]),
+    ("slm_batch_destroy", None, [_VP]),
+    ("slm_batch_workspace_size", C.c_int, [_VP, C.POINTER(C.c_size_t)]),
+    ("slm_batch_setup", C.c_int, [_VP, _VP, C.c_size_t, _VP]),
+    ("slm_batch_tune", C.c_int, [_VP, C.c_char_p, _VP]),
+    ("slm_batch_solve", C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(Stats),
+                                  C.POINTER(C.c_double), C.c_int, C.c_int, _VP]),
     ("slm_strerror", C.c_char_p, [C.c_int]),
     ("slm_last_error", C.c_char_p, [_VP]),
 ]

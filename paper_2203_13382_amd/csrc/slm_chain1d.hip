@@ -17,477 +17,11 @@
 // iterations.  Inner products and the Givens recurrence are FP64.  The
 // Krylov basis lives in registers (EPT values per thread per vector), so
 // coarse workgroups use at most 512 threads to get 256 VGPRs per lane.
-#include "slm_internal.h"
+#include "slm_kernels1d.h"
 
 namespace {
 
-constexpr int COARSE_MAXB = 512;
-
-// Interpolate the LDS slice `s` at the departure point of node i whose
-// displacement is d cells (xi = x_i - d h): x_E = x_{i - floor(d)},
-// eps = d - floor(d) (eq. depart_decompose).
-template <int P, typename T, typename TD>
-__device__ __forceinline__ T interp1(const T *__restrict__ s, int i, TD d, int nx, int nsmall)
-{
-    const TD fl = floor(d);
-    const T eps = T(d - fl);
-    const int first = stencil_first<T>(P, eps);
-    int base = i - int(fl) + first;
-    if (nsmall) {
-        base += base < 0 ? nx : 0;
-        base -= base >= nx ? nx : 0;
-    } else {
-        base = wrap_mod(base, nx);
-    }
-    T w[P + 1];
-    lagrange_weights<P, T>(-eps - T(first), w);
-    T acc = T(0);
-#pragma unroll
-    for (int j = 0; j <= P; ++j) {
-        int idx = base + j;
-        idx -= idx >= nx ? nx : 0;
-        acc += w[j] * s[idx];
-    }
-    return acc;
-}
-
-// Load the chain's start slice into LDS (and registers); optionally copy it
-// to the full-iterate output and, for chain 0 of a C-point sweep, to Cout[0].
-template <typename T, int EPT>
-__device__ __forceinline__ void chain_start(const ChainArgs &a, T *sl, T (&val)[EPT], long long n_first)
-{
-    const int tid = threadIdx.x, B = blockDim.x, j = blockIdx.x, nx = a.nx;
-    const T *Cin = static_cast<const T *>(a.Cin);
-    T *Vout = static_cast<T *>(a.Vout);
-    T *Cout = static_cast<T *>(a.Cout);
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int i = tid + e * B;
-        T s = T(0);
-        if (i < nx) {
-            if (Cin) s = Cin[(long long)j * a.cin_stride + i];
-            sl[i] = s;
-            if (Vout && a.write_start) Vout[n_first * a.S + i] = s;
-            if (Cout && j == 0 && a.cout_shift) Cout[i] = s;
-        }
-        val[e] = s;
-    }
-}
-
-// Write the chain's final state (Cout) and/or its C-point residual (R) with
-// the per-chain partial sum of squares.
-template <typename T, int EPT>
-__device__ __forceinline__ void chain_finish(const ChainArgs &a, const T (&val)[EPT], double *red, int rb)
-{
-    const int tid = threadIdx.x, B = blockDim.x, j = blockIdx.x, nx = a.nx;
-    const long long S = a.S;
-    T *Cout = static_cast<T *>(a.Cout);
-    if (Cout) {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            if (i < nx) Cout[(long long)(j + a.cout_shift) * S + i] = val[e];
-        }
-    }
-    if (a.R) {
-        const T *Cref = static_cast<const T *>(a.Cref);
-        T *R = static_cast<T *>(a.R);
-        double acc[1] = {0.0};
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            if (i < nx) {
-                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
-                R[(long long)(j + 1) * S + i] = r;
-                acc[0] += double(r) * double(r);
-            }
-        }
-        block_sum<1>(acc, red, rb);
-        if (tid == 0) a.partial[j] = acc[0];
-    }
-}
-
-// ------------------------------------------------------------------ level 0
-template <typename T, typename TD, int P, int EPT, bool DBUF, int PF>
-__global__ void __launch_bounds__(SLM_MAXB) fine1d(ChainArgs a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, B = blockDim.x, nx = a.nx;
-    const long long S = a.S;
-    T *sl0 = reinterpret_cast<T *>(smem);
-    T *sl1 = DBUF ? sl0 + nx : sl0;
-    const size_t off = ((size_t)(DBUF ? 2 : 1) * nx * sizeof(T) + 15) & ~size_t(15);
-    double *red = reinterpret_cast<double *>(smem + off);
-    const TD *disp = static_cast<const TD *>(a.disp);
-    const T *G = static_cast<const T *>(a.G);
-    T *Vout = static_cast<T *>(a.Vout);
-    const long long n_first = a.n_base + (long long)blockIdx.x * a.stride_chain;
-    const int ns = a.nsteps;
-
-    T val[EPT];
-    chain_start<T, EPT>(a, sl0, val, n_first);
-    TD ring[PF][EPT];                           // displacements of the next PF steps
-#pragma unroll
-    for (int u = 0; u < PF; ++u)
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = tid + e * B;
-            ring[u][e] = (u < ns && i < nx) ? disp[(n_first + u) * S + i] : TD(0);
-        }
-    __syncthreads();
-    int cur = 0;
-    for (int k0 = 0; k0 < ns; k0 += PF) {
-#pragma unroll
-        for (int u = 0; u < PF; ++u) {
-            const int k = k0 + u;
-            if (k >= ns) break;
-            const long long n = n_first + k;
-            TD dc[EPT];
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                dc[e] = ring[u][e];
-                const int i = tid + e * B;
-                if (k + PF < ns && i < nx) ring[u][e] = disp[(n + PF) * S + i];
-            }
-            const T *src = cur ? sl1 : sl0;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int i = tid + e * B;
-                val[e] = i < nx ? interp1<P, T, TD>(src, i, dc[e], nx, a.nsmall) : T(0);
-            }
-            if constexpr (!DBUF) __syncthreads();
-            T *dst = DBUF ? (cur ? sl0 : sl1) : sl0;
-            const bool wv = Vout && (k + 1 < ns || a.write_last);
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) {
-                const int i = tid + e * B;
-                if (i < nx) {
-                    if (G) val[e] += G[(n + 1) * S + i];
-                    dst[i] = val[e];
-                    if (wv) Vout[(n + 1) * S + i] = val[e];
-                }
-            }
-            if (DBUF) cur ^= 1;
-            __syncthreads();
-        }
-    }
-    chain_finish<T, EPT>(a, val, red, 0);
-}
-
-// ------------------------------------------------------------------ coarse levels
-// Element layout of the coarse kernel: thread t owns the EPT contiguous
-// nodes t*EPT .. t*EPT+EPT-1, so the D_{p+1} stencil needs only q neighbours
-// on each side from other threads.  Those come through an LDS exchange
-// buffer with one pad word per EPT nodes (no bank conflicts).
-template <int EPT>
-__device__ __forceinline__ int pidx(int i) { return i + i / EPT; }
-
-// LDS scalars used by thread 0 for the Givens recurrence.
-struct GmresScalars {
-    double R[SLM_KMAX][SLM_KMAX];   // R[col][row]
-    double cs[SLM_KMAX], sn[SLM_KMAX], g[SLM_KMAX + 1], z[SLM_KMAX];
-    int flag;
-};
-
-template <typename T, int P, int EPT>
-struct Gmres1D {
-    T V[SLM_KMAX + 1][EPT];
-    T w[EPT];
-    int k;
-
-    // One Arnoldi step JJ.  Returns true when the iteration stops before
-    // step JJ is taken.  xp: padded exchange buffer; sgp: sigma, padded.
-    template <int JJ>
-    __device__ __forceinline__ bool step(const double *sgp, T *xp, double *red, int &rb,
-                                          GmresScalars *gs, int kmax, double rtol, double beta, int nx)
-    {
-        int tid = threadIdx.x;
-        // Opaque per step: addresses derived from tid are recomputed in every
-        // Arnoldi step instead of being hoisted and held across all of them.
-        __asm__ volatile("" : "+v"(tid));
-        if (JJ >= kmax) return true;
-        const int i0 = tid * EPT;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (i0 + e < nx) xp[pidx<EPT>(i0 + e)] = V[JJ][e];
-        __syncthreads();
-        if (JJ > 0 && gs->flag) return true;
-        // w = V_JJ - sigma .* (D_{p+1} V_JJ) over the window i0-q .. i0+EPT-1+q
-        constexpr int q = DTaps<P>::q;
-        T win[EPT + 2 * q];
-#pragma unroll
-        for (int t = 0; t < q; ++t) {
-            int il = i0 - q + t;
-            il += il < 0 ? nx : 0;
-            int ir = i0 + EPT + t;
-            ir -= ir >= nx ? nx : 0;             // periodic (ragged tails wrap too)
-            win[t] = i0 < nx ? xp[pidx<EPT>(il)] : T(0);
-            win[EPT + q + t] = i0 < nx ? xp[pidx<EPT>(ir)] : T(0);
-        }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) win[q + e] = V[JJ][e];
-        // ragged tail: neighbours past nx wrap to the start of the slice
-        if (i0 + EPT > nx) {
-#pragma unroll
-            for (int e = 0; e < EPT + q; ++e) {
-                const int i = i0 + e;
-                if (i >= nx && i - nx < nx) win[q + e] = xp[pidx<EPT>(i - nx)];
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            if (i0 + e < nx) {
-                double dv = 0.0;
-#pragma unroll
-                for (int t = 0; t <= 2 * q; ++t) dv += DTaps<P>::t[t] * double(win[e + t]);
-                w[e] = T(double(V[JJ][e]) - sgp[pidx<EPT>(i0 + e)] * dv);
-            } else {
-                w[e] = T(0);
-            }
-        }
-        // classical Gram-Schmidt, twice; inner products are wave-uniform.
-        // The second pass also reduces ||w||^2, so ||w - V h2||^2 follows
-        // from Pythagoras (V orthonormal); an explicit reduction is used
-        // instead when that difference would cancel badly.
-        double h1[JJ + 1];
-#pragma unroll
-        for (int i = 0; i <= JJ; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) s += double(V[i][e] * w[e]);   // FP32 bulk: product in T
-            h1[i] = s;
-        }
-        block_sum_u<JJ + 1>(h1, red, rb);
-        rb ^= 1;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            T t = w[e];
-#pragma unroll
-            for (int i = 0; i <= JJ; ++i) t -= T(h1[i]) * V[i][e];
-            w[e] = t;
-        }
-        double h2[JJ + 2];
-#pragma unroll
-        for (int i = 0; i <= JJ; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) s += double(V[i][e] * w[e]);
-            h2[i] = s;
-        }
-        h2[JJ + 1] = 0.0;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) h2[JJ + 1] += double(w[e] * w[e]);
-        block_sum_u<JJ + 2>(h2, red, rb);
-        rb ^= 1;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            T t = w[e];
-#pragma unroll
-            for (int i = 0; i <= JJ; ++i) t -= T(h2[i]) * V[i][e];
-            w[e] = t;
-        }
-        double hh = 0.0;
-#pragma unroll
-        for (int i = 0; i <= JJ; ++i) hh += h2[i] * h2[i];
-        double hn2 = h2[JJ + 1] - hh;
-        if (!(hh <= 0.5 * h2[JJ + 1])) {           // uniform branch
-            double nn[1] = {0.0};
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) nn[0] += double(w[e] * w[e]);
-            block_sum_u<1>(nn, red, rb);
-            rb ^= 1;
-            hn2 = nn[0];
-        }
-        const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
-        if (tid == 0) {
-            double hc[JJ + 1];
-#pragma unroll
-            for (int i = 0; i <= JJ; ++i) hc[i] = h1[i] + h2[i];
-#pragma unroll
-            for (int i = 0; i < JJ; ++i) {          // previous rotations
-                const double ci = gs->cs[i], si = gs->sn[i];
-                const double t0 = ci * hc[i] + si * hc[i + 1];
-                const double t1 = -si * hc[i] + ci * hc[i + 1];
-                hc[i] = t0;
-                hc[i + 1] = t1;
-            }
-            const double den = sqrt(hc[JJ] * hc[JJ] + hn * hn);
-            const double c = hc[JJ] / den, sv = hn / den;
-            gs->cs[JJ] = c;
-            gs->sn[JJ] = sv;
-            hc[JJ] = den;
-            const double gj = gs->g[JJ];
-            gs->g[JJ + 1] = -sv * gj;
-            gs->g[JJ] = c * gj;
-#pragma unroll
-            for (int i = 0; i <= JJ; ++i) gs->R[JJ][i] = hc[i];
-            gs->flag = (hn == 0.0) || (fabs(sv * gj) <= rtol * beta);
-        }
-        k = JJ + 1;
-        const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) V[JJ + 1][e] = w[e] * T(inv);
-        return false;
-    }
-
-    // Solve [I - diag(sigma) D_{p+1}] y = x in place.  Returns iterations.
-    __device__ __forceinline__ int solve(T (&x)[EPT], const double *sgp, T *xp, double *red, int &rb,
-                                         GmresScalars *gs, int kmax, double rtol, int nx)
-    {
-        const int tid = threadIdx.x;
-        double bb[1] = {0.0};
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) bb[0] += double(x[e]) * double(x[e]);
-        if (tid == 0) gs->flag = 0;
-        block_sum_u<1>(bb, red, rb);
-        rb ^= 1;
-        const double beta = sqrt(bb[0]);
-        if (beta == 0.0 || kmax <= 0) {
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) x[e] = T(0);
-            return 0;
-        }
-        if (tid == 0) {
-            gs->g[0] = beta;
-            for (int i = 1; i <= SLM_KMAX; ++i) gs->g[i] = 0.0;
-        }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) V[0][e] = T(double(x[e]) / beta);
-        k = 0;
-        step<0>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<1>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<2>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<3>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<4>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<5>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<6>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<7>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) ||
-            step<8>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx) || step<9>(sgp, xp, red, rb, gs, kmax, rtol, beta, nx);
-        // back substitution R z = g (thread 0), then y = V z
-        if (tid == 0) {
-            for (int i = k - 1; i >= 0; --i) {
-                double s = gs->g[i];
-                for (int t = i + 1; t < k; ++t) s -= gs->R[t][i] * gs->z[t];
-                gs->z[i] = s / gs->R[i][i];
-            }
-        }
-        __syncthreads();
-        double y[EPT];
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) y[e] = 0.0;
-#pragma unroll
-        for (int i = 0; i < SLM_KMAX; ++i)
-            if (i < k) {
-                const double zi = gs->z[i];
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) y[e] += zi * double(V[i][e]);
-            }
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) x[e] = T(y[e]);
-        return k;
-    }
-};
-
-// LDS layout of the coarse kernel: slice (natural order) aliased with the
-// padded exchange buffer (the slice is dead while GMRES runs) | sigma
-// (padded) | reduction scratch | Givens scalars.
-template <typename T, int EPT>
-__host__ __device__ inline size_t coarse_lds_parts(int nx, size_t *o_sg, size_t *o_red, size_t *o_gs)
-{
-    auto al = [](size_t x) { return (x + 15) & ~size_t(15); };
-    const size_t np = (size_t)nx + nx / EPT + 1;
-    size_t o = al(np * sizeof(T));
-    *o_sg = o;
-    o = al(o + np * sizeof(double));
-    *o_red = o;
-    o = al(o + SLM_RED_DOUBLES * sizeof(double));
-    *o_gs = o;
-    return o + sizeof(GmresScalars);
-}
-
-template <typename T, int P, int EPT>
-__global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int tid = threadIdx.x, nx = a.nx, j = blockIdx.x;
-    const long long S = a.S;
-    size_t osg, ored, ogs;
-    coarse_lds_parts<T, EPT>(nx, &osg, &ored, &ogs);
-    T *sl = reinterpret_cast<T *>(smem);
-    T *xp = sl;
-    double *sgp = reinterpret_cast<double *>(smem + osg);
-    double *red = reinterpret_cast<double *>(smem + ored);
-    GmresScalars *gs = reinterpret_cast<GmresScalars *>(smem + ogs);
-    const double *disp = static_cast<const double *>(a.disp);
-    const T *Cin = static_cast<const T *>(a.Cin);
-    const T *G = static_cast<const T *>(a.G);
-    T *Vout = static_cast<T *>(a.Vout);
-    T *Cout = static_cast<T *>(a.Cout);
-    const long long n_first = a.n_base + (long long)j * a.stride_chain;
-    const int i0 = tid * EPT;
-
-    T val[EPT];
-#pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-        const int i = i0 + e;
-        T s = T(0);
-        if (i < nx) {
-            if (Cin) s = Cin[(long long)j * a.cin_stride + i];
-            sl[i] = s;
-            if (Vout && a.write_start) Vout[n_first * S + i] = s;
-            if (Cout && j == 0 && a.cout_shift) Cout[i] = s;
-        }
-        val[e] = s;
-    }
-    __syncthreads();
-    int rb = 0;
-    Gmres1D<T, P, EPT> gm;
-    unsigned long long nsolve = 0, niter = 0;
-    for (int k = 0; k < a.nsteps; ++k) {
-        const long long n = n_first + k;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = i0 + e;
-            if (i < nx) sgp[pidx<EPT>(i)] = a.sigma[n * S + i];
-            val[e] = i < nx ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
-        }
-        __syncthreads();                         // every read of the slice is done, sigma staged
-        niter += gm.solve(val, sgp, xp, red, rb, gs, a.kmax, a.rtol, nx);
-        ++nsolve;
-        const bool wv = Vout && (k + 1 < a.nsteps || a.write_last);
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = i0 + e;
-            if (i < nx) {
-                if (G) val[e] += G[(n + 1) * S + i];
-                sl[i] = val[e];
-                if (wv) Vout[(n + 1) * S + i] = val[e];
-            }
-        }
-        __syncthreads();
-    }
-    if (Cout) {
-#pragma unroll
-        for (int e = 0; e < EPT; ++e)
-            if (i0 + e < nx) Cout[(long long)(j + a.cout_shift) * S + i0 + e] = val[e];
-    }
-    if (a.R) {
-        const T *Cref = static_cast<const T *>(a.Cref);
-        T *R = static_cast<T *>(a.R);
-        double acc[1] = {0.0};
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            const int i = i0 + e;
-            if (i < nx) {
-                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
-                R[(long long)(j + 1) * S + i] = r;
-                acc[0] += double(r) * double(r);
-            }
-        }
-        block_sum<1>(acc, red, rb);
-        if (tid == 0) a.partial[j] = acc[0];
-    }
-    if (tid == 0 && a.counter) {
-        atomicAdd(a.counter, nsolve);
-        atomicAdd(a.counter + 1, niter);
-    }
-}
+using namespace slmk;
 
 // ------------------------------------------------------------------ launchers
 int lds_limit()
@@ -510,14 +44,6 @@ hipError_t launch(K kern, int nchains, int block, size_t lds, const ChainArgs &a
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nchains), dim3(block), lds, st, a);
     return hipGetLastError();
-}
-
-// Prefetch depth of the displacement ring: about 64 bytes per lane in
-// flight, between 1 and 4 steps.
-template <typename TD, int EPT>
-constexpr int pf_depth()
-{
-    return 64 / ((int)sizeof(TD) * EPT) < 1 ? 1 : (64 / ((int)sizeof(TD) * EPT) > 4 ? 4 : 64 / ((int)sizeof(TD) * EPT));
 }
 
 template <typename T, typename TD, int P, bool DBUF>

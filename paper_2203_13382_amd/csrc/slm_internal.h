@@ -90,4 +90,7 @@ hipError_t launch_axpy_slices(void *dst, long long dst_stride, const void *src, 
 hipError_t launch_copy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
                               int count, int S, int elem, hipStream_t st);
 
+// message returned by slm_last_error(NULL) (slm_plan.hip)
+void slm_set_error(const std::string &msg);
+
 inline char *ws_at(const slm_plan &P, size_t off) { return P.ws + off; }

@@ -152,6 +152,8 @@ struct Solver {
 
 }  // namespace
 
+void slm_set_error(const std::string &msg) { g_err = msg; }
+
 // ---------------------------------------------------------------------- ABI
 extern "C" {
 

@@ -145,8 +145,81 @@ class Plan:
         hist = (C.c_double * hist_cap)()
         rc = N.lib().slm_solve(self.h, _ptr(u0), _ptr(u), C.byref(st), hist, hist_cap, _stream(stream))
         N.check(rc, self.h)
-        stats = dict(iterations=st.iterations, status=N.STATUS.get(st.status, str(st.status)),
-                     n_levels=st.n_levels, rho0=st.rho0, rho_final=st.rho_final, solve_ms=st.solve_ms,
-                     point_updates=st.point_updates, gmres_solves=st.gmres_solves, gmres_iters=st.gmres_iters)
+        stats = _stats_dict(st)
         nh = min(hist_cap, st.iterations)
         return stats, np.array([hist[i] for i in range(nh)])
+
+
+def _stats_dict(st):
+    return dict(iterations=st.iterations, status=N.STATUS.get(st.status, str(st.status)),
+                n_levels=st.n_levels, rho0=st.rho0, rho_final=st.rho_final, solve_ms=st.solve_ms,
+                point_updates=st.point_updates, gmres_solves=st.gmres_solves, gmres_iters=st.gmres_iters)
+
+
+class Batch:
+    """Many independent 1D problems (a list of ``(Problem, Solver)``) solved
+    together by the batched V-cycle of ``slm_batch_solve``."""
+
+    def __init__(self, problems, precision="fp64", device="cuda"):
+        if torch is None:
+            raise N.NativeError("torch is required for device memory")
+        self.problems = list(problems)
+        self.n = len(self.problems)
+        self.precision = precision
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        descs = (N.Desc * max(1, self.n))()
+        self._keep = []
+        for i, (pr, sv) in enumerate(self.problems):
+            d, k = N.make_desc(pr, sv, precision)
+            descs[i] = d
+            self._keep.append(k)
+        self._descs = descs
+        h = C.c_void_p()
+        N.check(N.lib().slm_batch_create(descs, self.n, C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        N.check(N.lib().slm_batch_workspace_size(self.h, C.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                N.lib().slm_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def setup(self, stream=None):
+        if self.ws is None:
+            self._ws_raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self._ws_raw.data_ptr()) % 256
+            self.ws = self._ws_raw[off:off + self.ws_bytes]
+        N.check(N.lib().slm_batch_setup(self.h, _ptr(self.ws), self.ws_bytes, _stream(stream)))
+        return self
+
+    def tune(self, cache_path=None, stream=None):
+        cp = None if cache_path is None else str(cache_path).encode()
+        N.check(N.lib().slm_batch_tune(self.h, cp, _stream(stream)))
+        return self
+
+    def solve(self, u0s, us, use_graph=True, hist_cap=512, stream=None):
+        """Solve every problem in place on ``us[i]`` ([nt_i+1][nx_i] device
+        tensors whose C-points are the initial iterates); ``u0s[i]`` are the
+        initial conditions.  Returns (list of stats dicts, list of histories)."""
+        assert len(u0s) == self.n and len(us) == self.n
+        u0d = []
+        for i, (pr, _) in enumerate(self.problems):
+            assert us[i].dtype == self.dtype and us[i].is_contiguous() and us[i].numel() == (pr.nt + 1) * pr.nx
+            u0d.append(torch.as_tensor(u0s[i]).to(device=self.device, dtype=self.dtype).contiguous().reshape(pr.nx))
+        a0 = (C.c_void_p * self.n)(*[t.data_ptr() for t in u0d])
+        a1 = (C.c_void_p * self.n)(*[t.data_ptr() for t in us])
+        st = (N.Stats * self.n)()
+        hist = (C.c_double * (self.n * hist_cap))()
+        rc = N.lib().slm_batch_solve(self.h, a0, a1, st, hist, hist_cap, int(bool(use_graph)), _stream(stream))
+        N.check(rc)
+        stats = [_stats_dict(st[i]) for i in range(self.n)]
+        hs = [np.array([hist[i * hist_cap + k] for k in range(min(hist_cap, stats[i]["iterations"]))])
+              for i in range(self.n)]
+        return stats, hs

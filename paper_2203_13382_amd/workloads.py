@@ -114,3 +114,23 @@ def config(n: int, **over):
 def scaled(pr: Problem, nx: int, nt: int, cfl: float) -> Problem:
     """Same PDE on another mesh with dt = cfl*h."""
     return replace(pr, nx=nx, nt=nt, dt=cfl * 2.0 / nx)
+
+
+def batch_config(n: int = 64, seed: int = 4, cfl: float = 4.0, precision: str = "fp32", **over):
+    """The batch workload: ``n`` independent 1D problems of the PDE of
+    ``alpha_cfg12`` with drawn (nx, nt, p, amplitude) and dt = cfl*h, each
+    with the multilevel solver of the 1D workload (m = 8 down to <= 16
+    coarse points, FCF).  FP32 bulk stops at a relative tolerance of 1e-6
+    (the FP32 floor; FP64 keeps 1e-10).  Returns (list of (Problem,
+    Solver), precision)."""
+    from .inputs import batch_draws
+    tol = 1e-6 if precision == "fp32" else 1e-10
+    out = []
+    for d in batch_draws(n, seed):
+        pr = Problem(1, d["nx"], d["nt"], cfl * 2.0 / d["nx"], d["p"], d["p"], alpha_cfg12(d["amp"]))
+        sv = Solver(m=[8], coarsest_max_points=16, relax="FCF", gmres_kmax=10, gmres_rtol=1e-2,
+                    tol=tol, tol_mode="rel", max_iter=100)
+        pk = {k: v for k, v in over.items() if hasattr(pr, k)}
+        sk = {k: v for k, v in over.items() if hasattr(sv, k)}
+        out.append((replace(pr, **pk), replace(sv, **sk)))
+    return out, precision

@@ -1,0 +1,52 @@
+"""Writes tests/golden/cfg2_oracle.txt: the FP64 oracle's MGRIT run on the
+full config-2 workload (1D, nx=4096, nt=16384, dt=4h, p=r=3, m=8 multilevel
+to <=16 points, FCF, GMRES(10, 1e-2), rel. tol 1e-10; u0 = seeded Fourier IC,
+seed 0; initial iterate seed 1) and sampled values of its solution and of
+sequential stepping.  Calls only oracle/ and the seeded input generators.
+
+    python tests/golden/make_cfg2_golden.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2203_13382_amd import inputs as I  # noqa: E402
+from paper_2203_13382_amd import workloads as W  # noqa: E402
+
+
+def main():
+    O.build(force=False)
+    pr, sv, _ = W.config(2)
+    t0 = time.time()
+    ctx = O.Context(pr, sv)
+    u0 = I.initial_condition(pr, 0)
+    ui = I.initial_iterate(pr.nt, pr.S, sv.m[0], 1)
+    u, st, hist = ctx.mgrit(u0, ui)
+    t1 = time.time()
+    useq = O.seq_fine(pr, u0)
+    rng = np.random.default_rng(2024)
+    ns = rng.integers(0, pr.nt + 1, 256)
+    xs = rng.integers(0, pr.nx, 256)
+    out = os.path.join(HERE, "cfg2_oracle.txt")
+    with open(out, "w") as f:
+        f.write("# FP64 oracle, config-2 workload; written by tests/golden/make_cfg2_golden.py\n")
+        f.write(f"# oracle MGRIT wall time {t1 - t0:.1f} s (1 core)\n")
+        f.write(f"levels {' '.join(str(n) for n in ctx.N)}\n")
+        f.write(f"iterations {st['iterations']}\nstatus {st['status']}\n")
+        f.write(f"gmres_solves {st['gmres_solves']}\ngmres_iters {st['gmres_iters']}\n")
+        f.write("hist " + " ".join(f"{h:.17e}" for h in hist) + "\n")
+        f.write(f"max_abs_diff_mgrit_vs_seq {np.abs(u - useq).max():.6e}\n")
+        f.write(f"max_abs_seq {np.abs(useq).max():.17e}\n")
+        for n, i in zip(ns, xs):
+            f.write(f"sample {n} {i} {u[n, i]:.17e} {useq[n, i]:.17e}\n")
+    print("wrote", out, st)
+
+
+if __name__ == "__main__":
+    main()

@@ -122,3 +122,28 @@ def test_null_arguments():
     assert N.lib().slm_plan_create(None, None) == -1
     assert N.lib().slm_plan_workspace_size(None, None) == -1
     assert N.lib().slm_strerror(0) == b"ok"
+
+
+def _bdesc(p=3, relax="FCF"):
+    pr = W.Problem(1, 64, 32, 0.05, p, 3, W.alpha_cfg12())
+    sv = W.Solver(m=[4], relax=relax)
+    return N.make_desc(pr, sv, "fp64")
+
+
+def test_batch_create_rejects_unsupported():
+    """Batch descriptors are validated before any device call."""
+    L = N.lib()
+    h = C.c_void_p()
+    assert L.slm_batch_create(None, 1, C.byref(h)) == -1
+    d1, k1 = _bdesc()
+    d2, k2 = _bdesc(p=2)
+    arr = (N.Desc * 2)(d1, d2)
+    assert L.slm_batch_create(arr, 2, C.byref(h)) == -2 and not h.value
+    assert b"odd p" in L.slm_last_error(None)
+    d3, k3 = _bdesc(relax="F")
+    arr = (N.Desc * 2)(d1, d3)
+    assert L.slm_batch_create(arr, 2, C.byref(h)) == -2
+    arr = (N.Desc * 1)(d1)
+    assert L.slm_batch_create(arr, 0, C.byref(h)) == -1
+    assert L.slm_batch_setup(None, None, 0, None) == -1
+    assert L.slm_batch_solve(None, None, None, None, None, 0, 0, None) == -1

@@ -1,0 +1,202 @@
+"""GPU parity of the batched 1D solver (slm_batch_*: persistent level-0 and
+coarse sweeps over a work list, device-side stopping test, graph-replayed
+V-cycles, autotuner) against the FP64 oracle, problem by problem, through the
+C ABI.
+
+The small batches mix slice sizes (several workgroup tiles, ragged tails),
+time-step counts, interpolation orders 1/3/5, two-level, multilevel and
+single-level hierarchies.  The full-size batch (64 drawn problems, FP32 bulk)
+is checked on every problem's stopping status and, for sampled problems, on
+the oracle's sequential solution.
+"""
+import numpy as np
+import pytest
+
+from paper_2203_13382_amd import inputs as I
+from paper_2203_13382_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed(relax):
+    a = W.alpha_cfg12
+    if relax == "FCF":
+        return [
+            (W.Problem(1, 200, 96, 2.3 * 2 / 200, 5, 5, a(0.3)), W.Solver(m=[4], coarsest_max_points=2)),
+            (W.Problem(1, 64, 256, 0.85 * 2 / 64, 1, 1, a(0.5)),
+             W.Solver(m=[4], max_levels=2, gmres_rtol=0.0, tol=1e-10, tol_mode="abs")),
+            (W.Problem(1, 1500, 64, 3.1 * 2 / 1500, 3, 3, a(0.5)), W.Solver(m=[4, 2], coarsest_max_points=2)),
+            (W.Problem(1, 600, 128, 4.0 * 2 / 600, 3, 3, a(0.7)), W.Solver(m=[8], coarsest_max_points=16)),
+            (W.Problem(1, 96, 8, 1.5 * 2 / 96, 3, 3, a(0.4)), W.Solver(m=[8], coarsest_max_points=16)),
+            (W.Problem(1, 4096, 32, 4.0 * 2 / 4096, 1, 1, a(0.6)), W.Solver(m=[4], coarsest_max_points=2)),
+        ]
+    return [
+        (W.Problem(1, 300, 48, 2.0 * 2 / 300, 3, 3, a(0.5)), W.Solver(m=[4], relax="F", coarsest_max_points=2)),
+        (W.Problem(1, 128, 64, 1.2 * 2 / 128, 5, 5, a(0.25)),
+         W.Solver(m=[2, 4], relax="F", coarsest_max_points=2, gmres_rtol=0.0)),
+        (W.Problem(1, 777, 40, 3.3 * 2 / 777, 1, 1, a(0.8)), W.Solver(m=[4], relax="F", max_levels=2)),
+    ]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(1e-300, np.abs(b).max())
+
+
+def _inputs(probs, dtype=np.float64):
+    u0s, uis = [], []
+    for i, (pr, sv) in enumerate(probs):
+        u0s.append(I.initial_condition(pr, 10 + i).astype(dtype))
+        uis.append(I.initial_iterate(pr.nt, pr.S, sv.m[0], 20 + i).astype(dtype))
+    return u0s, uis
+
+
+_cache = {}
+
+
+def _solved(relax, torch, use_graph=True):
+    key = (relax, use_graph)
+    if key not in _cache:
+        from paper_2203_13382_amd import Batch
+        probs = _mixed(relax)
+        b = Batch(probs, "fp64").setup()
+        u0s, uis = _inputs(probs)
+        us = [torch.from_numpy(u).cuda() for u in uis]
+        st, hs = b.solve(u0s, us, use_graph=use_graph)
+        _cache[key] = (probs, b, u0s, uis, [u.cpu().numpy() for u in us], st, hs)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_batch_matches_oracle(relax, oracle, torch):
+    probs, b, u0s, uis, us, st, hs = _solved(relax, torch)
+    for i, (pr, sv) in enumerate(probs):
+        ctx = oracle.Context(pr, sv)
+        u_ref, st_ref, h_ref = ctx.mgrit(u0s[i], uis[i])
+        assert st[i]["n_levels"] == st_ref["n_levels"], i
+        assert st[i]["status"] == st_ref["status"], i
+        if st_ref["n_levels"] > 1:
+            assert st[i]["iterations"] == st_ref["iterations"], i
+            assert len(hs[i]) == len(h_ref)
+            assert np.abs(hs[i] - h_ref).max() <= 1e-8 * h_ref[0], i
+            big = h_ref > 1e-7 * h_ref[0]
+            assert np.abs(hs[i][big] / h_ref[big] - 1).max() < 1e-6, i
+            assert st[i]["gmres_solves"] == st_ref["gmres_solves"], i
+            # A coarse solve whose right-hand side is exactly zero takes no
+            # GMRES iteration, one whose right-hand side is rounding noise
+            # takes kmax when rtol = 0.  F-relaxation propagates the first
+            # C-points exactly, so their residuals are exactly zero on one
+            # side and rounding noise on the other: the totals may differ
+            # by a few percent.  The exact count is compared with the
+            # single-problem GPU path in test_batch_matches_single_plans.
+            assert abs(st[i]["gmres_iters"] - st_ref["gmres_iters"]) <= max(
+                3 * sv.gmres_kmax, 0.05 * st_ref["gmres_iters"]), i
+        assert _rel(us[i], u_ref) < 1e-9, (i, _rel(us[i], u_ref))
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_batch_graph_replay_equals_eager(relax, torch):
+    g = _solved(relax, torch, True)
+    e = _solved(relax, torch, False)
+    for i in range(len(g[0])):
+        assert np.array_equal(g[4][i], e[4][i]), i
+        assert np.array_equal(g[6][i], e[6][i]), i
+        assert g[5][i]["iterations"] == e[5][i]["iterations"]
+    # a second graph solve replays the cached graph
+    from paper_2203_13382_amd import Batch  # noqa: F401
+    probs, b, u0s, uis = g[0], g[1], g[2], g[3]
+    us = [torch.from_numpy(u).cuda() for u in uis]
+    st, hs = b.solve(u0s, us, use_graph=True)
+    for i in range(len(probs)):
+        assert np.array_equal(us[i].cpu().numpy(), g[4][i]), i
+        assert np.array_equal(hs[i], g[6][i]), i
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_batch_matches_single_plans(relax, torch):
+    from paper_2203_13382_amd import Plan
+    probs, b, u0s, uis, us, st, hs = _solved(relax, torch)
+    for i, (pr, sv) in enumerate(probs):
+        plan = Plan(pr, sv, "fp64").setup()
+        u = torch.from_numpy(uis[i]).cuda()
+        s1, h1 = plan.solve(torch.from_numpy(u0s[i]), u)
+        assert s1["iterations"] == st[i]["iterations"] and s1["status"] == st[i]["status"], i
+        assert s1["point_updates"] == st[i]["point_updates"], i
+        assert s1["gmres_solves"] == st[i]["gmres_solves"], i
+        assert s1["gmres_iters"] == st[i]["gmres_iters"], i
+        assert _rel(us[i], u.cpu().numpy()) < 1e-13, i
+
+
+def test_batch_tune_and_cache(torch, tmp_path):
+    from paper_2203_13382_amd import Batch
+    probs = _mixed("FCF")
+    b = Batch(probs, "fp64").setup()
+    u0s, uis = _inputs(probs)
+    us = [torch.from_numpy(u).cuda() for u in uis]
+    st0, h0 = b.solve(u0s, us)
+    ref = [u.cpu().numpy() for u in us]
+    cache = tmp_path / "tune.txt"
+    b.tune(str(cache))
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and len(lines[0].split()) == 4
+    b.tune(str(cache))                      # second call reads the cached choice
+    assert cache.read_text().splitlines() == lines
+    b.tune()                                # no cache: times the candidates again
+    us = [torch.from_numpy(u).cuda() for u in uis]
+    st1, h1 = b.solve(u0s, us)
+    for i in range(len(probs)):             # the launch shape never changes the arithmetic
+        assert np.array_equal(us[i].cpu().numpy(), ref[i]), i
+        assert np.array_equal(h1[i], h0[i]), i
+
+
+def test_batch_fp32_bulk(oracle, torch):
+    import dataclasses
+    from paper_2203_13382_amd import Batch
+    probs = [(pr, dataclasses.replace(sv, tol=1e-6, tol_mode="rel")) for pr, sv in _mixed("FCF")]
+    b = Batch(probs, "fp32").setup()
+    u0s, uis = _inputs(probs, np.float32)
+    us = [torch.from_numpy(u).cuda() for u in uis]
+    st, _ = b.solve(u0s, us)
+    for i, (pr, sv) in enumerate(probs):
+        assert st[i]["status"] in ("converged", "stagnated"), (i, st[i])
+        useq = oracle.seq_fine(pr, u0s[i].astype(np.float64))
+        assert _rel(us[i].cpu().numpy(), useq) < 2e-7 * pr.nt + 1e-5, i
+
+
+def test_batch_full_size_workload(oracle, torch):
+    """The 64-problem FP32-bulk batch at its drawn sizes, tuned and solved
+    with graph replay: every problem stops at the tolerance (or the FP32
+    floor); the three cheapest problems are compared with the oracle's
+    sequential solution at every time point, two sampled larger ones with
+    the single-problem GPU path."""
+    from paper_2203_13382_amd import Batch
+    probs, prec = W.batch_config()
+    b = Batch(probs, prec).setup()
+    b.tune()
+    u0s = [I.initial_condition(pr, 10 + i).astype(np.float32) for i, (pr, sv) in enumerate(probs)]
+    us = [torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 20 + i).astype(np.float32)).cuda()
+          for i, (pr, sv) in enumerate(probs)]
+    st, hs = b.solve(u0s, us, use_graph=True)
+    for i in range(len(probs)):
+        assert st[i]["status"] in ("converged", "stagnated"), (i, st[i])
+        assert st[i]["iterations"] <= 30, (i, st[i])
+    cheap = sorted(range(len(probs)), key=lambda i: probs[i][0].nx * probs[i][0].nt)[:3]
+    for i in cheap:
+        pr = probs[i][0]
+        useq = oracle.seq_fine(pr, u0s[i].astype(np.float64))
+        assert _rel(us[i].cpu().numpy(), useq) < 2e-7 * pr.nt + 1e-5, i
+    from paper_2203_13382_amd import Plan
+    rng = np.random.default_rng(5)
+    for i in rng.choice([k for k in range(len(probs)) if k not in cheap], 2, replace=False):
+        pr, sv = probs[i]
+        plan = Plan(pr, sv, prec).setup()
+        u = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 20 + i).astype(np.float32)).cuda()
+        s1, _ = plan.solve(torch.from_numpy(u0s[i]), u)
+        assert s1["status"] == st[i]["status"], i
+        assert _rel(us[i].cpu().numpy(), u.cpu().numpy()) < 1e-5, i
