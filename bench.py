@@ -44,7 +44,81 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the level-0 F+C sweep kernel and a 1 GiB device copy (for counter runs)")
+    ap.add_argument("--workload", choices=["1d", "batch"], default="1d",
+                    help="1d: the single 1D problem (default line); batch: 64 drawn 1D problems solved together")
     return ap.parse_args()
+
+
+def batch_bench(args):
+    """64 independent 1D problems of drawn (nx, nt, p, amplitude), FP32 bulk
+    with FP64 tracing and norms, solved together: persistent work-list
+    sweeps, device-side stopping test, one captured V-cycle replayed.  One
+    step = setup of every problem + the batched solve.  The sequential
+    baseline steps all 64 problems concurrently (one persistent launch over
+    the problems)."""
+    import torch
+    from paper_2203_13382_amd import Batch
+    from paper_2203_13382_amd import inputs as I
+    from paper_2203_13382_amd import workloads as W
+    probs, prec = W.batch_config()
+    dt = np.float32 if prec == "fp32" else np.float64
+    b = Batch(probs, prec).setup()
+    t0 = time.perf_counter()
+    b.tune()
+    tune_s = time.perf_counter() - t0
+    u0s = [torch.from_numpy(I.initial_condition(pr, 10 + i).astype(dt)).cuda() for i, (pr, sv) in enumerate(probs)]
+    uis = [torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 20 + i).astype(dt)).cuda()
+           for i, (pr, sv) in enumerate(probs)]
+    us = [torch.empty_like(u) for u in uis]
+    last = {}
+
+    def one_step():
+        b.setup()
+        for u, ui in zip(us, uis):
+            u.copy_(ui)
+        last["st"], _ = b.solve(u0s, us, use_graph=True)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(args.steps):
+        e0.record(stream)
+        one_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.mean(times))
+    st = last["st"]
+    upd = sum(s["point_updates"] for s in st)
+    its = [s["iterations"] for s in st]
+    # sequential stepping of every problem, all problems concurrently
+    seq = Batch([(pr, W.Solver(m=[2], max_levels=1)) for pr, sv in probs], prec).setup()
+    useq = [torch.empty_like(u) for u in uis]
+
+    def seq_step():
+        seq.setup()
+        seq.solve(u0s, useq, use_graph=False)
+    seq_ms = timed(torch, seq_step, max(1, args.steps))
+    err = max(float((u.double() - v.double()).abs().max() / v.double().abs().max()) for u, v in zip(us, useq))
+    pts = sum(pr.nt * pr.S for pr, sv in probs)
+    out = {
+        "metric": METRIC, "value": upd / (ms * 1e-3), "unit": "point-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch of {len(probs)} 1D problems, nx 256..8192, nt 1024..16384, p in 1/3/5, "
+                               f"dt=0.85h, alpha amplitudes U[0.2,0.8] (seed 4), m=8 to <=16 points, FCF, "
+                               f"FP32 bulk + FP64 tracing/norms, rel. tol 1e-6",
+                   "problems": len(probs), "space_time_points": pts, "precision": prec},
+        "mgrit": {"time_to_tol_ms": ms, "point_updates": upd, "iterations_min": min(its),
+                  "iterations_max": max(its), "statuses": sorted(set(s["status"] for s in st)),
+                  "max_rel_err_vs_seq": err, "tune_s": tune_s},
+        "seq": {"total_ms": seq_ms, "point_updates_per_s": pts / (seq_ms * 1e-3)},
+        "speedup_vs_seq": seq_ms / ms,
+    }
+    print(json.dumps(out))
 
 
 def kernel_only(args):
@@ -71,14 +145,16 @@ def kernel_only(args):
 
 def measured_traffic():
     """HBM bytes per launch of the level-0 sweep from the committed counter
-    summary, or None once the kernel source differs from the one profiled."""
+    summary, or None once the kernel sources (device code of the sweep and
+    its helpers) differ from the ones profiled."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "cfg2_kernels.md")
-    src = os.path.join(ROOT, "paper_2203_13382_amd", "csrc", "slm_chain1d.hip")
+    csrc = os.path.join(ROOT, "paper_2203_13382_amd", "csrc")
+    srcs = [os.path.join(csrc, f) for f in ("slm_kernels1d.h", "slm_chain1d.hip", "slm_common.h")]
     try:
         kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
                   and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()[:16]
         return int(kv["traffic_bytes_per_launch"]) if kv.get("kernel_source_sha256_16", "").strip() == sha else None
     except (OSError, KeyError, ValueError):
         return None
@@ -130,6 +206,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.kernel_only:
         return kernel_only(args)
+    if args.workload == "batch":
+        return batch_bench(args)
     dev = torch.device("cuda")
 
     pr, sv, _ = W.config(2)

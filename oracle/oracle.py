@@ -101,6 +101,16 @@ def lib():
         L.slmo_level_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.slmo_apply_phi.argtypes = [C.c_void_p, C.c_int, C.c_int, _D, _D]
         L.slmo_mgrit.argtypes = [C.c_void_p, _D, _D, _D, C.c_int, C.POINTER(CStats)]
+        L.slmo_apply_BT.argtypes = [C.c_int, C.c_int, C.c_int, _D, _D, _D, _D]
+        L.slmo_bsolve_T.argtypes = [C.c_int, C.c_int, C.c_int, _D, _D, _D, _D, C.c_int, C.c_double]
+        L.slmo_interp_T.argtypes = [C.c_int, C.c_int, C.c_int, _D, _D, _D, _D]
+        L.slmo_apply_phi_T.argtypes = [C.c_void_p, C.c_int, C.c_int, _D, _D]
+        L.slmo_adjoint_seq.argtypes = [C.POINTER(CProblem), _D, _D]
+        L.slmo_mgrit_adjoint.argtypes = [C.c_void_p, _D, _D, _D, C.c_int, C.POINTER(CStats)]
+        L.slmo_erk_back_tangent.argtypes = [C.POINTER(CProblem), C.c_double, C.c_double, C.c_double,
+                                            C.c_double, _D, _D]
+        L.slmo_weights_deps.argtypes = [C.c_int, C.c_double, _D]
+        L.slmo_grad_theta.argtypes = [C.POINTER(CProblem), _D, _D, _D]
         _lib = L
     return _lib
 
@@ -258,6 +268,76 @@ def seq_fine(pr, u0):
     return u
 
 
+def apply_BT(dim, nx, p, sx, sy, v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros_like(v)
+    lib().slmo_apply_BT(dim, nx, p, _ptr(np.ascontiguousarray(sx)),
+                        _ptr(None if sy is None else np.ascontiguousarray(sy)), _ptr(v), _ptr(out))
+    return out
+
+
+def bsolve_T(dim, nx, p, sx, sy, b, kmax, rtol):
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    y = np.zeros_like(b)
+    it = lib().slmo_bsolve_T(dim, nx, p, _ptr(np.ascontiguousarray(sx)),
+                             _ptr(None if sy is None else np.ascontiguousarray(sy)),
+                             _ptr(b), _ptr(y), kmax, float(rtol))
+    return y, it
+
+
+def interp_T(dim, nx, p, xi, eta, lam):
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    out = np.zeros_like(lam)
+    lib().slmo_interp_T(dim, nx, p, _ptr(np.ascontiguousarray(xi)),
+                        _ptr(None if eta is None else np.ascontiguousarray(eta)), _ptr(lam), _ptr(out))
+    return out
+
+
+def adjoint_seq(pr, lamT):
+    """lambda_n for n = 0..nt from lambda_nt = lamT (sequential S_n^T sweep)."""
+    S = S_of(pr)
+    lam = np.zeros((pr.nt + 1, S))
+    k = c_problem(pr)
+    lib().slmo_adjoint_seq(C.byref(k.cp), _ptr(np.ascontiguousarray(lamT, dtype=np.float64).reshape(-1)),
+                           _ptr(lam))
+    return lam
+
+
+def n_theta(pr):
+    return len(pr.alpha) + (len(pr.beta or []) if pr.dim == 2 else 0)
+
+
+def erk_back_tangent(pr, x, y, t_arr, dt):
+    nq = n_theta(pr)
+    dxi, deta = np.zeros(16), np.zeros(16)
+    k = c_problem(pr)
+    lib().slmo_erk_back_tangent(C.byref(k.cp), x, y, t_arr, dt, _ptr(dxi), _ptr(deta))
+    return dxi[:nq].copy(), deta[:nq].copy()
+
+
+def weights_deps(p, eps):
+    w = np.zeros(p + 1)
+    lib().slmo_weights_deps(p, eps, _ptr(w))
+    return w
+
+
+def grad_theta(pr, u_all, lam_all):
+    g = np.zeros(16)
+    k = c_problem(pr)
+    lib().slmo_grad_theta(C.byref(k.cp), _ptr(np.ascontiguousarray(u_all, dtype=np.float64)),
+                          _ptr(np.ascontiguousarray(lam_all, dtype=np.float64)), _ptr(g))
+    return g[:n_theta(pr)].copy()
+
+
+def loss_and_gradient(pr, u0, u_obs):
+    """L = 1/2 ||u_nt - u_obs||^2 of sequential stepping, dL/du0 and dL/dtheta
+    (theta = the alpha term coefficients, then the beta ones in 2D)."""
+    u = seq_fine(pr, u0)
+    r = u[-1] - np.asarray(u_obs, dtype=np.float64).reshape(-1)
+    lam = adjoint_seq(pr, r)
+    return 0.5 * float(r @ r), lam[0].copy(), grad_theta(pr, u, lam)
+
+
 def hierarchy(nt, sv):
     N = (C.c_int * 64)(); mm = (C.c_int * 64)()
     k = c_solver(sv)
@@ -314,3 +394,24 @@ class Context:
                      gmres_iters=st.gmres_iters)
         nh = min(hist_cap, st.iterations) if st.n_levels > 1 else 0
         return u, stats, hist[:nh].copy()
+
+    def apply_phi_T(self, level, n, v):
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+        out = np.zeros_like(v)
+        lib().slmo_apply_phi_T(self.h, level, n, _ptr(v), _ptr(out))
+        return out
+
+    def mgrit_adjoint(self, lamT, mu_init, hist_cap=1000):
+        """MGRIT on the adjoint system in reverse time: returns (mu, stats,
+        history) with mu[k] = lambda_{nt-k}; ``mu_init``'s C-points are the
+        initial iterate."""
+        mu = np.ascontiguousarray(mu_init, dtype=np.float64).reshape(self.pr.nt + 1, self.S).copy()
+        hist = np.zeros(hist_cap)
+        st = CStats()
+        lib().slmo_mgrit_adjoint(self.h, _ptr(np.ascontiguousarray(lamT, dtype=np.float64).reshape(-1)),
+                                 _ptr(mu), _ptr(hist), hist_cap, C.byref(st))
+        stats = dict(iterations=st.iterations, status=STATUS[st.status], n_levels=st.n_levels,
+                     rho0=st.rho0, rho_final=st.rho_final, gmres_solves=st.gmres_solves,
+                     gmres_iters=st.gmres_iters)
+        nh = min(hist_cap, st.iterations) if st.n_levels > 1 else 0
+        return mu, stats, hist[:nh].copy()

@@ -280,6 +280,39 @@ void slmo_apply_B(int dim, int nx, int p, const double *sx, const double *sy,
         }
 }
 
+/* out = B^T v = [I - D_x diag(sx) - D_y diag(sy)] v: the transpose of
+ * slmo_apply_B (D_{p+1} is symmetric), used by the adjoint coarse operator. */
+void slmo_apply_BT(int dim, int nx, int p, const double *sx, const double *sy,
+                   const double *v, double *out)
+{
+    double taps[8];
+    int q = (p + 1) / 2;
+    slmo_dop_taps(p, taps);
+    if (dim == 1) {
+        for (int i = 0; i < nx; i++) {
+            double d = 0.0;
+            for (int k = -q; k <= q; k++) {
+                long long t = pmod(i + k, nx);
+                d += taps[k + q] * sx[t] * v[t];
+            }
+            out[i] = v[i] - d;
+        }
+        return;
+    }
+    for (int j = 0; j < nx; j++)
+        for (int i = 0; i < nx; i++) {
+            double dx = 0.0, dy = 0.0;
+            for (int k = -q; k <= q; k++) {
+                long long tx = (long long)j * nx + pmod(i + k, nx);
+                long long ty = pmod(j + k, nx) * nx + i;
+                dx += taps[k + q] * sx[tx] * v[tx];
+                dy += taps[k + q] * sy[ty] * v[ty];
+            }
+            long long id = (long long)j * nx + i;
+            out[id] = v[id] - dx - dy;
+        }
+}
+
 static double dot(long long n, const double *a, const double *b)
 {
     double s = 0.0;
@@ -294,8 +327,25 @@ static double dot(long long n, const double *a, const double *b)
  * rotations for the least-squares problem; the relative residual is the
  * Givens estimate |g_{j+1}|/||b||, tested after each iteration; rtol = 0 runs
  * all kmax iterations; b = 0 returns y = 0.  Returns the iterations done. */
+static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy,
+                     const double *b, double *y, int kmax, double rtol, int transpose);
+
 int slmo_bsolve(int dim, int nx, int p, const double *sx, const double *sy,
                 const double *b, double *y, int kmax, double rtol)
+{
+    return bsolve_gen(dim, nx, p, sx, sy, b, y, kmax, rtol, 0);
+}
+
+/* The same GMRES for the transposed system B^T y = b (adjoint coarse
+ * operator). */
+int slmo_bsolve_T(int dim, int nx, int p, const double *sx, const double *sy,
+                  const double *b, double *y, int kmax, double rtol)
+{
+    return bsolve_gen(dim, nx, p, sx, sy, b, y, kmax, rtol, 1);
+}
+
+static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy,
+                      const double *b, double *y, int kmax, double rtol, int transpose)
 {
     long long S = dim == 1 ? nx : (long long)nx * nx;
     double beta = sqrt(dot(S, b, b));
@@ -312,7 +362,8 @@ int slmo_bsolve(int dim, int nx, int p, const double *sx, const double *sy,
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < kmax; j++) {
-        slmo_apply_B(dim, nx, p, sx, sy, V + (long long)j * S, w);
+        if (transpose) slmo_apply_BT(dim, nx, p, sx, sy, V + (long long)j * S, w);
+        else slmo_apply_B(dim, nx, p, sx, sy, V + (long long)j * S, w);
         for (int i = 0; i <= j; i++) hcol[i] = 0.0;
         for (int pass = 0; pass < 2; pass++) {       /* CGS, twice */
             double hp[64];
@@ -462,6 +513,7 @@ struct slmo_ctx {
     double *v[SLMO_MAXL], *g[SLMO_MAXL];    /* MGRIT iterate and RHS */
     double *t0, *t1;                        /* work slices */
     long long gmres_solves, gmres_iters;
+    int adjoint;                            /* 1: reverse-time adjoint system */
 };
 
 /* Level hierarchy (Sec. 2.2 and 3.4): coarsen by m_l while the coarse level
@@ -632,12 +684,22 @@ void slmo_apply_phi(slmo_ctx *c, int l, int n, const double *in, double *out)
     free(tmp);
 }
 
+/* The level-l one-step operator of the system being solved: Phi_l(n) for
+ * the forward system; for the adjoint system in reverse time (step k maps
+ * lambda_{N-k} to lambda_{N-k-1}) the transpose of the forward step it
+ * mirrors, Phi_l(N_l-1-k)^T. */
+static void phi_sys(slmo_ctx *c, int l, int n, const double *in, double *out)
+{
+    if (c->adjoint) slmo_apply_phi_T(c, l, c->N[l] - 1 - n, in, out);
+    else slmo_apply_phi(c, l, n, in, out);
+}
+
 /* v[n] = Phi_l(n-1) v[n-1] + g[n]  (eq. one-step at level l) */
 static void step_to(slmo_ctx *c, int l, int n)
 {
     long long S = c->S;
     double *v = c->v[l];
-    slmo_apply_phi(c, l, n - 1, v + (long long)(n - 1) * S, v + (long long)n * S);
+    phi_sys(c, l, n - 1, v + (long long)(n - 1) * S, v + (long long)n * S);
     if (c->g[l])
         for (long long i = 0; i < S; i++) v[(long long)n * S + i] += c->g[l][(long long)n * S + i];
 }
@@ -667,7 +729,7 @@ static double residual(slmo_ctx *c, int l)
     double *v = c->v[l], *gc = c->g[l + 1], s2 = 0.0;
     for (int j = 1; j <= nc; j++) {
         long long n = (long long)j * m;
-        slmo_apply_phi(c, l, (int)n - 1, v + (n - 1) * S, c->t0);
+        phi_sys(c, l, (int)n - 1, v + (n - 1) * S, c->t0);
         for (long long i = 0; i < S; i++) {
             double r = (c->g[l] ? c->g[l][n * S + i] : 0.0) + c->t0[i] - v[n * S + i];
             gc[(long long)j * S + i] = r;
@@ -760,4 +822,255 @@ int slmo_mgrit(slmo_ctx *c, const double *u0, double *u, double *hist, int hist_
     if (st) *st = s;
     c->v[0] = NULL;
     return s.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the one-step system (gradients of a final-time misfit)         */
+/* ------------------------------------------------------------------------ */
+/* The discrete forward problem is the space-time system A u = g of Sec. 2.2
+ * with u_{n+1} = S_n u_n.  For L = 1/2 ||u_nt - u_obs||^2 the adjoint
+ * system A^T lambda = dL/du reads lambda_nt = u_nt - u_obs and
+ * lambda_n = S_n^T lambda_{n+1}; then dL/du0 = lambda_0 and, for a
+ * coefficient theta of the wave-speed terms,
+ *     dL/dtheta = sum_n lambda_{n+1}^T (dS_n/dtheta) u_n,
+ * where S_n depends on theta through its departure points only. */
+
+/* out = S^T lam: the transpose of slmo_interp, written as the scatter of
+ * every node's interpolation weights. */
+void slmo_interp_T(int dim, int nx, int p, const double *xi, const double *eta,
+                   const double *lam, double *out)
+{
+    double wx[8], wy[8];
+    long long S = dim == 1 ? nx : (long long)nx * nx;
+    for (long long k = 0; k < S; k++) out[k] = 0.0;
+    if (dim == 1) {
+        for (int i = 0; i < nx; i++) {
+            long long E; double eps; int ell, rr;
+            slmo_decompose(nx, xi[i], &E, &eps);
+            slmo_stencil(p, eps, &ell, &rr);
+            slmo_weights(p, eps, wx);
+            for (int j = -ell; j <= rr; j++) out[pmod(E + j, nx)] += wx[j + ell] * lam[i];
+        }
+        return;
+    }
+    for (long long k = 0; k < S; k++) {
+        long long E, N; double eps, nu; int lx, rx, ly, ry;
+        slmo_decompose(nx, xi[k], &E, &eps);
+        slmo_decompose(nx, eta[k], &N, &nu);
+        slmo_stencil(p, eps, &lx, &rx);
+        slmo_stencil(p, nu, &ly, &ry);
+        slmo_weights(p, eps, wx);
+        slmo_weights(p, nu, wy);
+        for (int b = -ly; b <= ry; b++) {
+            long long row = pmod(N + b, nx);
+            for (int a = -lx; a <= rx; a++)
+                out[row * nx + pmod(E + a, nx)] += wy[b + ly] * wx[a + lx] * lam[k];
+        }
+    }
+}
+
+/* Phi_l(n)^T.  Level 0: S_n^T.  Modified coarse operator (eq.
+ * Phi_multilevel / BEOper_2D): (B^{-1} S_l)^T = S_l^T (B^T)^{-1}, the inverse
+ * again by GMRES.  Reading: the adjoint uses the same GMRES settings as the
+ * forward solve.  Ideal: the product of the transposed fine steps in reverse
+ * order.  Rediscretised: S_l^T. */
+void slmo_apply_phi_T(slmo_ctx *c, int l, int n, const double *in, double *out)
+{
+    const slmo_problem *pr = &c->pr;
+    long long S = c->S;
+    if (l == 0 || c->sv.coarse_op == SLMO_COARSE_REDISC) {
+        slmo_interp_T(pr->dim, pr->nx, pr->p, c->dep[l][0] + (long long)n * S,
+                      pr->dim == 2 ? c->dep[l][1] + (long long)n * S : NULL, in, out);
+        return;
+    }
+    if (c->sv.coarse_op == SLMO_COARSE_IDEAL) {
+        double *a = (double *)malloc(sizeof(double) * S), *b = (double *)malloc(sizeof(double) * S);
+        memcpy(a, in, sizeof(double) * S);
+        for (long long s = c->M[l] - 1; s >= 0; s--) {
+            long long f = (long long)n * c->M[l] + s;
+            slmo_interp_T(pr->dim, pr->nx, pr->p, c->dep[0][0] + f * S,
+                          pr->dim == 2 ? c->dep[0][1] + f * S : NULL, a, b);
+            double *t = a; a = b; b = t;
+        }
+        memcpy(out, a, sizeof(double) * S);
+        free(a); free(b);
+        return;
+    }
+    double *tmp = (double *)malloc(sizeof(double) * S);
+    int it = slmo_bsolve_T(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
+                           pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL,
+                           in, tmp, c->sv.gmres_kmax, c->sv.gmres_rtol);
+    c->gmres_solves++;
+    c->gmres_iters += it;
+    slmo_interp_T(pr->dim, pr->nx, pr->p, c->dep[l][0] + (long long)n * S,
+                  pr->dim == 2 ? c->dep[l][1] + (long long)n * S : NULL, tmp, out);
+    free(tmp);
+}
+
+/* Sequential adjoint sweep: lam is [(nt+1)][S]; lam[nt] = lamT and
+ * lam[n] = S_n^T lam[n+1] (the plain definition of the adjoint solution). */
+void slmo_adjoint_seq(const slmo_problem *pr, const double *lamT, double *lam)
+{
+    long long S = pr->dim == 1 ? pr->nx : (long long)pr->nx * pr->nx;
+    double *xi = (double *)malloc(sizeof(double) * S);
+    double *eta = (double *)malloc(sizeof(double) * S);
+    memcpy(lam + (long long)pr->nt * S, lamT, sizeof(double) * S);
+    for (int n = pr->nt - 1; n >= 0; n--) {
+        slmo_depart_fine(pr, n, xi, eta);
+        slmo_interp_T(pr->dim, pr->nx, pr->p, xi, eta, lam + (long long)(n + 1) * S,
+                      lam + (long long)n * S);
+    }
+    free(xi); free(eta);
+}
+
+/* Linear MGRIT on the adjoint system in reverse time: mu_k = lambda_{nt-k},
+ * mu_0 = lamT, mu_{k+1} = S_{nt-1-k}^T mu_k.  The level hierarchy, coarse
+ * departure points and sigma of the forward context are reused: reverse
+ * coarse step K of level l mirrors forward coarse step N_l-1-K, whose
+ * transpose is its coarse operator.  Same driver, cycle and stopping test as
+ * slmo_mgrit.  mu is [(nt+1)][S]; its C-points are the initial iterate. */
+int slmo_mgrit_adjoint(slmo_ctx *c, const double *lamT, double *mu, double *hist, int hist_cap,
+                       slmo_stats *st)
+{
+    c->adjoint = 1;
+    int rc = slmo_mgrit(c, lamT, mu, hist, hist_cap, st);
+    c->adjoint = 0;
+    return rc;
+}
+
+/* Derivative of one term cos(kx pi x + px) cos(ky pi y + py) cos(kt pi t + pt)
+ * (without its coefficient) with respect to x and y. */
+static void term_grad(const slmo_term *t, double x, double y, double time, double *val,
+                      double *gx, double *gy)
+{
+    double ax = t->kx * SLMO_PI * x + t->px, ay = t->ky * SLMO_PI * y + t->py;
+    double ct = cos(t->kt * SLMO_PI * time + t->pt);
+    *val = cos(ax) * cos(ay) * ct;
+    *gx = -t->kx * SLMO_PI * sin(ax) * cos(ay) * ct;
+    *gy = -t->ky * SLMO_PI * cos(ax) * sin(ay) * ct;
+}
+
+/* Tangent of the backward ERK departure point (slmo_erk_back) with respect
+ * to every term coefficient: dxi[q], deta[q] for q = 0..n_alpha-1 (alpha
+ * terms) then n_alpha..n_alpha+n_beta-1 (beta terms).  The ERK stages are
+ * differentiated exactly (forward-mode through the stage recursion). */
+void slmo_erk_back_tangent(const slmo_problem *pr, double x, double y, double t_arr,
+                           double dt, double *dxi, double *deta)
+{
+    double c[6], a[36], b[6], kx[6], ky[6], X[6], Y[6];
+    int s = slmo_erk_tableau(pr->r, c, a, b);
+    int nq = pr->n_alpha + (pr->dim == 2 ? pr->n_beta : 0);
+    double hs = -dt;
+    for (int i = 0; i < s; i++) {
+        X[i] = x; Y[i] = y;
+        for (int j = 0; j < i; j++) {
+            X[i] += hs * a[i * 6 + j] * kx[j];
+            Y[i] += hs * a[i * 6 + j] * ky[j];
+        }
+        double ti = t_arr + c[i] * hs;
+        kx[i] = slmo_wave(pr->alpha, pr->n_alpha, X[i], Y[i], ti);
+        ky[i] = pr->dim == 2 ? slmo_wave(pr->beta, pr->n_beta, X[i], Y[i], ti) : 0.0;
+    }
+    for (int q = 0; q < nq; q++) {
+        double dkx[6], dky[6];
+        for (int i = 0; i < s; i++) {
+            double dX = 0.0, dY = 0.0;
+            for (int j = 0; j < i; j++) {
+                dX += hs * a[i * 6 + j] * dkx[j];
+                dY += hs * a[i * 6 + j] * dky[j];
+            }
+            double ti = t_arr + c[i] * hs;
+            double ax = 0.0, ay = 0.0, bx = 0.0, by = 0.0, pa = 0.0, pb = 0.0, v, gx, gy;
+            for (int k = 0; k < pr->n_alpha; k++) {
+                term_grad(&pr->alpha[k], X[i], Y[i], ti, &v, &gx, &gy);
+                ax += pr->alpha[k].coef * gx;
+                ay += pr->alpha[k].coef * gy;
+                if (k == q) pa = v;
+            }
+            if (pr->dim == 2)
+                for (int k = 0; k < pr->n_beta; k++) {
+                    term_grad(&pr->beta[k], X[i], Y[i], ti, &v, &gx, &gy);
+                    bx += pr->beta[k].coef * gx;
+                    by += pr->beta[k].coef * gy;
+                    if (pr->n_alpha + k == q) pb = v;
+                }
+            dkx[i] = ax * dX + (pr->dim == 2 ? ay * dY : 0.0) + pa;
+            dky[i] = pr->dim == 2 ? bx * dX + by * dY + pb : 0.0;
+        }
+        double sx = 0.0, sy = 0.0;
+        for (int i = 0; i < s; i++) { sx += b[i] * dkx[i]; sy += b[i] * dky[i]; }
+        dxi[q] = hs * sx;
+        deta[q] = pr->dim == 2 ? hs * sy : 0.0;
+    }
+}
+
+/* Derivatives of the Lagrange weights of slmo_weights with respect to eps
+ * (odd p: the stencil does not change with eps):
+ * d/deps w_j(-eps) = -sum_{l != j} prod_{k != j,l} (z - k) / prod_{k != j} (j - k). */
+void slmo_weights_deps(int p, double eps, double *dw)
+{
+    int ell, rr;
+    slmo_stencil(p, eps, &ell, &rr);
+    double z = -eps;
+    for (int j = -ell; j <= rr; j++) {
+        double den = 1.0, sum = 0.0;
+        for (int k = -ell; k <= rr; k++)
+            if (k != j) den *= (double)(j - k);
+        for (int l = -ell; l <= rr; l++) {
+            if (l == j) continue;
+            double prod = 1.0;
+            for (int k = -ell; k <= rr; k++)
+                if (k != j && k != l) prod *= z - k;
+            sum += prod;
+        }
+        dw[j + ell] = -sum / den;
+    }
+}
+
+/* dL/dtheta = sum_n lam[n+1]^T (dS_n/dtheta) u[n] for every term
+ * coefficient (order of slmo_erk_back_tangent).  u and lam are
+ * [(nt+1)][S].  eps = ceil(s) - s with s = (xi+1)/h, so d eps = -d xi / h
+ * away from mesh nodes. */
+void slmo_grad_theta(const slmo_problem *pr, const double *u, const double *lam, double *grad)
+{
+    int nx = pr->nx, p = pr->p, dim = pr->dim;
+    int nq = pr->n_alpha + (dim == 2 ? pr->n_beta : 0);
+    long long S = dim == 1 ? nx : (long long)nx * nx;
+    double h = 2.0 / nx;
+    double wx[8], wy[8], dwx[8], dwy[8], dxi[2 * 8], deta[2 * 8];
+    for (int q = 0; q < nq; q++) grad[q] = 0.0;
+    for (int n = 0; n < pr->nt; n++) {
+        const double *un = u + (long long)n * S, *ln = lam + (long long)(n + 1) * S;
+        double t_arr = (n + 1) * pr->dt;
+        for (long long k = 0; k < S; k++) {
+            double x = -1.0 + (k % nx) * h, y = dim == 2 ? -1.0 + (k / nx) * h : 0.0;
+            double xd, yd;
+            slmo_erk_back(pr, x, y, t_arr, pr->dt, &xd, &yd);
+            slmo_erk_back_tangent(pr, x, y, t_arr, pr->dt, dxi, deta);
+            long long E, N = 0; double eps, nu = 0.0; int lx, rx, ly = 0, ry = 0;
+            slmo_decompose(nx, xd, &E, &eps);
+            slmo_stencil(p, eps, &lx, &rx);
+            slmo_weights(p, eps, wx);
+            slmo_weights_deps(p, eps, dwx);
+            double gx = 0.0, gy = 0.0;      /* d u_{n+1}[k] / d eps, / d nu */
+            if (dim == 1) {
+                for (int a = -lx; a <= rx; a++) gx += dwx[a + lx] * un[pmod(E + a, nx)];
+            } else {
+                slmo_decompose(nx, yd, &N, &nu);
+                slmo_stencil(p, nu, &ly, &ry);
+                slmo_weights(p, nu, wy);
+                slmo_weights_deps(p, nu, dwy);
+                for (int b = -ly; b <= ry; b++) {
+                    long long row = pmod(N + b, nx);
+                    for (int a = -lx; a <= rx; a++) {
+                        double uv = un[row * nx + pmod(E + a, nx)];
+                        gx += dwx[a + lx] * wy[b + ly] * uv;
+                        gy += wx[a + lx] * dwy[b + ly] * uv;
+                    }
+                }
+            }
+            for (int q = 0; q < nq; q++)
+                grad[q] += ln[k] * (gx * (-dxi[q] / h) + (dim == 2 ? gy * (-deta[q] / h) : 0.0));
+        }
+    }
 }

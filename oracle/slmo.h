@@ -100,6 +100,23 @@ void  slmo_apply_phi(slmo_ctx *c, int level, int n, const double *in, double *ou
 int   slmo_mgrit(slmo_ctx *c, const double *u0, double *u, double *hist, int hist_cap,
                  slmo_stats *st);
 
+/* ---- adjoint (gradient of 1/2 ||u_nt - u_obs||^2) ---- */
+void slmo_apply_BT(int dim, int nx, int p, const double *sx, const double *sy,
+                   const double *v, double *out);
+int  slmo_bsolve_T(int dim, int nx, int p, const double *sx, const double *sy,
+                   const double *b, double *y, int kmax, double rtol);
+void slmo_interp_T(int dim, int nx, int p, const double *xi, const double *eta,
+                   const double *lam, double *out);
+void slmo_apply_phi_T(slmo_ctx *c, int level, int n, const double *in, double *out);
+void slmo_adjoint_seq(const slmo_problem *pr, const double *lamT, double *lam_all);
+int  slmo_mgrit_adjoint(slmo_ctx *c, const double *lamT, double *mu, double *hist, int hist_cap,
+                        slmo_stats *st);
+void slmo_erk_back_tangent(const slmo_problem *pr, double x, double y, double t_arr,
+                           double dt, double *dxi, double *deta);
+void slmo_weights_deps(int p, double eps, double *dw);
+void slmo_grad_theta(const slmo_problem *pr, const double *u_all, const double *lam_all,
+                     double *grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,7 +116,7 @@ def scaled(pr: Problem, nx: int, nt: int, cfl: float) -> Problem:
     return replace(pr, nx=nx, nt=nt, dt=cfl * 2.0 / nx)
 
 
-def batch_config(n: int = 64, seed: int = 4, cfl: float = 4.0, precision: str = "fp32", **over):
+def batch_config(n: int = 64, seed: int = 4, cfl: float = 0.85, precision: str = "fp32", **over):
     """The batch workload: ``n`` independent 1D problems of the PDE of
     ``alpha_cfg12`` with drawn (nx, nt, p, amplitude) and dt = cfl*h, each
     with the multilevel solver of the 1D workload (m = 8 down to <= 16
