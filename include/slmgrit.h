@@ -83,6 +83,8 @@ typedef struct {
     int tol_mode;              /* SLM_TOL_ABS or SLM_TOL_REL */
     int max_iter;              /* cycle cap, >= 1 */
     int precision;             /* SLM_FP64 or SLM_FP32_BULK */
+    int adjoint;               /* 1: also size the workspace for slm_adjoint (needs SLM_FP64,
+                                  odd p and at least two levels); 0: forward only */
 } slm_desc;
 
 typedef struct slm_plan slm_plan;
@@ -166,6 +168,37 @@ int slm_step(slm_plan *plan, const void *d_u0, void *d_u, int store_all, void *s
  * the stats status (>= 0) or an error (< 0). */
 int slm_solve(slm_plan *plan, const void *d_u0, void *d_u, slm_stats *stats,
               double *h_hist, int hist_cap, void *stream);
+
+/* Forward MGRIT that keeps only the C-points (every m_0-th time slice), the
+ * checkpoints from which slm_adjoint recomputes the F-points.  d_c is
+ * [(nt/m_0)+1][S] of T, in/out: on entry the initial iterate at the
+ * C-points (slice 0 is overwritten by u_0), on exit the converged C-values
+ * (slice nt/m_0 is the approximation of u_nt).  Statistics as slm_solve;
+ * the final F-relaxation is not run.  Needs at least two levels. */
+int slm_solve_cpoints(slm_plan *plan, const void *d_u0, void *d_c, slm_stats *stats,
+                      double *h_hist, int hist_cap, void *stream);
+
+/* Gradient of a final-time misfit L(u_nt) through the one-step system
+ * (discrete adjoint of eq. one-step): with lambda_nt = d_lamT (= dL/du_nt,
+ * [S] double) the adjoint system lambda_n = S_n^T lambda_{n+1} is solved by
+ * linear MGRIT in reverse time on the plan's hierarchy, its coarse operator
+ * being the transpose S_l^T [I - D_x diag(sx) - D_y diag(sy)]^{-1} of eq.
+ * (Phi_multilevel) / (BEOper_2D), with the descriptor's relaxation, GMRES
+ * settings and tolerance.  Then, coarse interval by interval, the F-points
+ * of u are recomputed from the checkpoints d_c (slm_solve_cpoints output)
+ * and lambda is swept back through them, accumulating
+ *     dL/dtheta_q = sum_n lambda_{n+1}^T (dS_n/dtheta_q) u_n
+ * for every wave-speed coefficient (the alpha terms' coef, then the beta
+ * terms'), with dS_n/dtheta from the Lagrange weights' derivative and the
+ * tangent of the ERK departure trace.  Outputs: d_grad_u0 = lambda_0 ([S]
+ * double), h_grad_theta[n_alpha + n_beta] (host), statistics and residual
+ * history of the adjoint MGRIT.  The transposed interpolation is a gather
+ * over an inverse stencil index built once per plan (integer counting
+ * sort); floating-point sums run in a fixed order, so results are
+ * deterministic.  Needs a plan created with desc.adjoint = 1. */
+int slm_adjoint(slm_plan *plan, const void *d_c, const void *d_lamT, void *d_grad_u0,
+                double *h_grad_theta, slm_stats *stats, double *h_hist, int hist_cap,
+                void *stream);
 
 /* ---- Many independent 1D problems solved together (a batch) --------------
  * The level-0 relaxation sweeps of every problem run as one persistent

@@ -35,7 +35,7 @@ class Desc(C.Structure):
                 ("max_levels", C.c_int), ("coarsest_max_points", C.c_int),
                 ("relax", C.c_int), ("gmres_kmax", C.c_int), ("gmres_rtol", C.c_double),
                 ("tol", C.c_double), ("tol_mode", C.c_int), ("max_iter", C.c_int),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("adjoint", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -58,6 +58,9 @@ SIGNATURES = [
     ("slm_relax", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]),
     ("slm_step", C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
     ("slm_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats), C.POINTER(C.c_double), C.c_int, _VP]),
+    ("slm_solve_cpoints", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats), C.POINTER(C.c_double), C.c_int, _VP]),
+    ("slm_adjoint", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(C.c_double), C.POINTER(Stats),
+                              C.POINTER(C.c_double), C.c_int, _VP]),
     ("slm_batch_create", C.c_int, [C.POINTER(Desc), C.c_int, C.POINTER(_VP)]),
     ("slm_batch_destroy", None, [_VP]),
     ("slm_batch_workspace_size", C.c_int, [_VP, C.POINTER(C.c_size_t)]),
@@ -106,7 +109,7 @@ class _Keep:
     pass
 
 
-def make_desc(pr, sv, precision: str):
+def make_desc(pr, sv, precision: str, adjoint: bool = False):
     """Fill an ``slm_desc`` from a Problem/Solver pair; returns (desc, keepalive)."""
     keep = _Keep()
     keep.a = terms_array(pr.alpha)
@@ -115,5 +118,5 @@ def make_desc(pr, sv, precision: str):
     d = Desc(pr.dim, pr.nx, pr.nt, float(pr.dt), pr.p, pr.r, keep.a, len(pr.alpha),
              keep.b, len(pr.beta or []), keep.m, len(sv.m), sv.max_levels, sv.coarsest_max_points,
              {"F": 0, "FCF": 1}[sv.relax], sv.gmres_kmax, float(sv.gmres_rtol), float(sv.tol),
-             {"abs": 0, "rel": 1}[sv.tol_mode], sv.max_iter, {"fp64": 0, "fp32": 1}[precision])
+             {"abs": 0, "rel": 1}[sv.tol_mode], sv.max_iter, {"fp64": 0, "fp32": 1}[precision], int(bool(adjoint)))
     return d, keep

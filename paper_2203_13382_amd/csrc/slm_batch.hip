@@ -15,6 +15,7 @@
 // reads one counter per cycle.  Per problem the arithmetic and the order of
 // operations are those of slm_solve (linear V-cycle, Sec. 2.2).
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -178,7 +179,7 @@ struct slm_batch {
         int n;                // items / descriptors
         int block;
         size_t lds;
-        long long maxelems;   // copies: largest count*S
+        long long maxelems;   // copies: largest count*S; level-0 sweeps: largest slice
     };
     int n = 0;
     std::vector<slm_plan *> plans;
@@ -250,18 +251,40 @@ struct Builder {
 
     explicit Builder(const slm_batch &b) : B(b) {}
 
+    // Level-0 items are grouped by (p, workgroup size, elements per thread)
+    // of their slice, the shape the per-level kernel would use.
+    static void fine_shape(int nx, int &block, int &ept)
+    {
+        block = nx >= SLM_MAXB ? SLM_MAXB : (nx + 63) / 64 * 64;
+        const int e = (nx + block - 1) / block;
+        ept = e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : 8;
+    }
     void fine(const std::vector<BItem> &v)
     {
-        for (int p : {1, 3, 5}) {
+        std::vector<std::array<int, 3>> keys;
+        for (const auto &it : v) {
+            int b, e;
+            fine_shape(it.a.nx, b, e);
+            const std::array<int, 3> k{it.a.p, b, e};
+            if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+        }
+        std::sort(keys.begin(), keys.end());
+        for (const auto &k : keys) {
             std::vector<BItem> g;
-            for (const auto &it : v)
-                if (it.a.p == p) g.push_back(it);
-            if (g.empty()) continue;
+            int nxg = 0;
+            for (const auto &it : v) {
+                int b, e;
+                fine_shape(it.a.nx, b, e);
+                if (it.a.p == k[0] && b == k[1] && e == k[2]) {
+                    g.push_back(it);
+                    nxg = std::max(nxg, it.a.nx);
+                }
+            }
             if (B.order_desc)     // largest items first: the tail of the list is short work
                 std::stable_sort(g.begin(), g.end(), [](const BItem &x, const BItem &y) {
                     return (long long)x.a.nx * x.a.nsteps > (long long)y.a.nx * y.a.nsteps;
                 });
-            pend.push_back(Pending{0, p, 0, (int)items.size(), (int)g.size(), 0, 0, 0});
+            pend.push_back(Pending{0, k[0], k[2], (int)items.size(), (int)g.size(), k[1], 0, nxg});
             items.insert(items.end(), g.begin(), g.end());
         }
     }
@@ -340,21 +363,22 @@ hipError_t plaunch(K k, int grid, int block, size_t lds, hipStream_t st, const B
     return hipGetLastError();
 }
 
-// Level-0 launch shape from the largest slice of the batch (threads past a
-// smaller slice hold no nodes); workgroups per CU come from slm_batch_tune.
+// Level-0 launch of one (p, workgroup size, elements per thread) group;
+// LDS is sized for the group's largest slice.  Workgroups per CU come from
+// slm_batch_tune.
 template <typename T>
 hipError_t fine_launch(const slm_batch &B, const slm_batch::Op &o, hipStream_t st, unsigned *next)
 {
     const BItem *items = (const BItem *)(B.ws + o.off);
     const BCtl *ctl = (const BCtl *)(B.ws + B.o_ctl);
-    const int block = B.nx_max >= SLM_MAXB ? SLM_MAXB : (B.nx_max + 63) / 64 * 64;
-    const int ept = (B.nx_max + block - 1) / block;
-    const bool dbuf = 2ull * B.nx_max * sizeof(T) + SLM_RED_DOUBLES * sizeof(double) + 16 <= (size_t)lds_cap();
-    const size_t lds = (((size_t)(dbuf ? 2 : 1) * B.nx_max * sizeof(T) + 15) & ~size_t(15)) +
+    const long long nxg = o.maxelems;
+    const bool dbuf = 2ull * nxg * sizeof(T) + SLM_RED_DOUBLES * sizeof(double) + 16 <= (size_t)lds_cap();
+    const size_t lds = (((size_t)(dbuf ? 2 : 1) * nxg * sizeof(T) + 15) & ~size_t(15)) +
                        SLM_RED_DOUBLES * sizeof(double);
-    const int grid = std::max(1, std::min(o.n, B.grid_mult * B.cus));
+    const int grid = std::max(1, std::min(o.n, B.grid_mult * B.cus * (SLM_MAXB / o.block)));
+    const int block = o.block;
 #define FB(PP, E, D) plaunch(fine_batch<T, T, PP, E, D, pf_depth<T, E>()>, grid, block, lds, st, items, o.n, next, ctl)
-#define FBE(PP, D) switch (ept) { case 1: return FB(PP, 1, D); case 2: return FB(PP, 2, D); case 3: case 4: return FB(PP, 4, D); default: return FB(PP, 8, D); }
+#define FBE(PP, D) switch (o.ept) { case 1: return FB(PP, 1, D); case 2: return FB(PP, 2, D); case 4: return FB(PP, 4, D); default: return FB(PP, 8, D); }
 #define FBP(D) switch (o.p) { case 1: FBE(1, D); case 3: FBE(3, D); default: FBE(5, D); }
     if (dbuf) FBP(true);
     FBP(false);

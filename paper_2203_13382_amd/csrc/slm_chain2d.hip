@@ -1,4 +1,5 @@
-// slm_chain2d.hip -- relaxation sweeps on a periodic 2D mesh.
+// slm_chain2d.hip -- relaxation sweeps on a periodic 2D mesh (and the
+// sweeps of the adjoint system, 1D and 2D).
 //
 // A 2D slice (nx*nx values) does not fit in one CU's LDS, so a sweep over m
 // level steps is a sequence of launches, one per step index, each advancing
@@ -15,6 +16,12 @@
 // systems, inner products are per-block FP64 partial sums reduced in a fixed
 // order, and a one-thread-per-system kernel runs the Givens recurrence.
 // Converged systems skip their work through a per-system flag.
+//
+// Adjoint mode (ChainArgs.adj) runs the same sweeps on the reverse-time
+// adjoint system: level 0 applies S_n^T of the mirrored forward step, the
+// coarse levels S_l^T [I - D_x diag(sx) - D_y diag(sy)]^{-1}: the GMRES
+// right-hand side is the incoming slice, the matvec the transposed one, and
+// the transposed interpolation follows the solve.
 #include "slm_internal.h"
 
 namespace {
@@ -168,16 +175,21 @@ __global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long lo
         V0[id] = T(double(b[c * S + id]) * inv);
 }
 
-// w = V_j - sx .* (D_x V_j) - sy .* (D_y V_j); partials of V_i . w, i <= j.
+// w = V_j - sx .* (D_x V_j) - sy .* (D_y V_j), or for the adjoint system
+// (transpose) w = V_j - D_x (sx .* V_j) - D_y (sy .* V_j); partials of
+// V_i . w, i <= j.  1D slices have no y term.  The sigma of step n (or of
+// the mirrored step Nl-1-n when rev) is used.
 template <typename T, int P>
 __global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__restrict__ W, long long S, int nx,
                                                   const double *__restrict__ sig, long long plane, long long n_first,
-                                                  int stride, int j, const Gs2 *gs, double *part)
+                                                  int stride, int j, const Gs2 *gs, double *part, int dim,
+                                                  int transpose, int rev, int Nl)
 {
     __shared__ double red[SLM_RED_DOUBLES];
     const int c = blockIdx.y;
     if (gs[c].done) return;
-    const long long n = n_first + (long long)c * stride;
+    const long long n0 = n_first + (long long)c * stride;
+    const long long n = rev ? Nl - 1 - n0 : n0;
     const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
     const T *vj = Vc + (long long)j * S;
     const double *sx = sig + n * S, *sy = sig + plane + n * S;
@@ -186,19 +198,25 @@ __global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__r
 #pragma unroll
     for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
     for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
-        const int i = (int)(id % nx), jr = (int)(id / nx);
+        const int i = (int)(id % nx), jr = dim == 2 ? (int)(id / nx) : 0;
         double dxv = 0.0, dyv = 0.0;
 #pragma unroll
         for (int t = -q; t <= q; ++t) {
-            int ii = i + t, jj = jr + t;
+            int ii = i + t;
             ii += ii < 0 ? nx : 0;
             ii -= ii >= nx ? nx : 0;
-            jj += jj < 0 ? nx : 0;
-            jj -= jj >= nx ? nx : 0;
-            dxv += DTaps<P>::t[t + q] * double(vj[(long long)jr * nx + ii]);
-            dyv += DTaps<P>::t[t + q] * double(vj[(long long)jj * nx + i]);
+            const long long ix = (long long)jr * nx + ii;
+            dxv += DTaps<P>::t[t + q] * (transpose ? sx[ix] * double(vj[ix]) : double(vj[ix]));
+            if (dim == 2) {
+                int jj = jr + t;
+                jj += jj < 0 ? nx : 0;
+                jj -= jj >= nx ? nx : 0;
+                const long long iy = (long long)jj * nx + i;
+                dyv += DTaps<P>::t[t + q] * (transpose ? sy[iy] * double(vj[iy]) : double(vj[iy]));
+            }
         }
-        const T w = T(double(vj[id]) - sx[id] * dxv - sy[id] * dyv);
+        const double yterm = dim == 2 ? (transpose ? dyv : sy[id] * dyv) : 0.0;
+        const T w = T(double(vj[id]) - (transpose ? dxv : sx[id] * dxv) - yterm);
         W[c * S + id] = w;
 #pragma unroll
         for (int k = 0; k <= SLM_KMAX; ++k)
@@ -360,14 +378,18 @@ hipError_t launch_step(int p, dim3 grid, hipStream_t st, const T *src, long long
 
 template <typename T>
 hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, const T *V, T *W, long long S, int nx, const double *sig,
-                         long long plane, long long n_first, int stride, int j, const Gs2 *gs, double *part)
+                         long long plane, long long n_first, int stride, int j, const Gs2 *gs, double *part, int dim,
+                         int transpose, int rev, int Nl)
 {
+#define MV(PP) hipLaunchKernelGGL((g2_matvec<T, PP>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, \
+                                  j, gs, part, dim, transpose, rev, Nl)
     switch (p) {
-    case 1: hipLaunchKernelGGL((g2_matvec<T, 1>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, j, gs, part); break;
-    case 3: hipLaunchKernelGGL((g2_matvec<T, 3>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, j, gs, part); break;
-    case 5: hipLaunchKernelGGL((g2_matvec<T, 5>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, j, gs, part); break;
+    case 1: MV(1); break;
+    case 3: MV(3); break;
+    case 5: MV(5); break;
     default: return hipErrorInvalidValue;
     }
+#undef MV
     return hipGetLastError();
 }
 
@@ -398,7 +420,12 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
     for (int k = 0; k < a.nsteps; ++k) {
         const bool last = k + 1 == a.nsteps;
         T *vo = (Vout && (!last || a.write_last)) ? Vout : nullptr;
-        if (level == 0) {
+        if (a.adj && level == 0) {
+            // adjoint: transposed SL step of the mirrored forward step
+            e = launch_stepT(P, 0, nch, (const double *)bufs[cur], S, (double *)bufs[cur ^ 1], S, n_first0 + k,
+                             a.stride_chain, 1, (const double *)a.G, (double *)vo, st);
+            if (e != hipSuccess) return e;
+        } else if (level == 0) {
             if (P.d.precision == SLM_FP32_BULK)
                 e = launch_step<T, float>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S,
                                           (const float *)ws_at(P, L.disp), plane, nx, n_first0 + k, a.stride_chain,
@@ -409,11 +436,17 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                                            a.stride_chain, (const T *)a.G, vo);
             if (e != hipSuccess) return e;
         } else {
-            // interpolation into the GMRES right-hand side
+            // forward: interpolation into the GMRES right-hand side; adjoint:
+            // the incoming slice is the right-hand side of the transposed solve
             T *bb = (T *)ws_at(P, P.g2b);
-            e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bb, S, (const double *)ws_at(P, L.disp), plane,
-                                       nx, n_first0 + k, a.stride_chain, nullptr, nullptr);
-            if (e != hipSuccess) return e;
+            const T *rhs = bb;
+            if (a.adj) {
+                rhs = bufs[cur];
+            } else {
+                e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bb, S, (const double *)ws_at(P, L.disp),
+                                           plane, nx, n_first0 + k, a.stride_chain, nullptr, nullptr);
+                if (e != hipSuccess) return e;
+            }
             T *V = (T *)ws_at(P, P.g2v);
             T *W = (T *)ws_at(P, P.g2w);
             Gs2 *gs = (Gs2 *)ws_at(P, P.g2s);
@@ -421,11 +454,11 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             double *pc = pb + (long long)P.capg * nb * NPART;
             double *hk = pc + (long long)P.capg * nb * NPART;
             const double *sig = (const double *)ws_at(P, L.sigma);
-            hipLaunchKernelGGL(g2_norm0<T>, grid, dim3(TPB), 0, st, bb, S, pa);
-            hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, bb, S, pa, nb, V, gs, a.kmax);
+            hipLaunchKernelGGL(g2_norm0<T>, grid, dim3(TPB), 0, st, rhs, S, pa);
+            hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, rhs, S, pa, nb, V, gs, a.kmax);
             for (int j = 0; j < a.kmax; ++j) {
                 if ((e = launch_matvec<T>(P.d.p, grid, st, V, W, S, nx, sig, plane, n_first0 + k, a.stride_chain, j, gs,
-                                          pa)) != hipSuccess)
+                                          pa, P.d.dim, a.adj, a.adj, L.N)) != hipSuccess)
                     return e;
                 hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, pa, pb, 1, hk);
                 hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, pb, pc, 0, (double *)nullptr);
@@ -433,8 +466,18 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                                    a.rtol, a.kmax);
                 hipLaunchKernelGGL(g2_normalize<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs);
             }
-            hipLaunchKernelGGL(g2_combine<T>, grid, dim3(TPB), 0, st, V, S, gs, bufs[cur ^ 1], S, n_first0 + k,
-                               a.stride_chain, (const T *)a.G, vo);
+            if (a.adj) {
+                // y = (B^T)^{-1} rhs, then the transposed interpolation S_l^T y
+                hipLaunchKernelGGL(g2_combine<T>, grid, dim3(TPB), 0, st, V, S, gs, bb, S, n_first0 + k,
+                                   a.stride_chain, (const T *)nullptr, (T *)nullptr);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                e = launch_stepT(P, level, nch, (const double *)bb, S, (double *)bufs[cur ^ 1], S, n_first0 + k,
+                                 a.stride_chain, 1, (const double *)a.G, (double *)vo, st);
+                if (e != hipSuccess) return e;
+            } else {
+                hipLaunchKernelGGL(g2_combine<T>, grid, dim3(TPB), 0, st, V, S, gs, bufs[cur ^ 1], S, n_first0 + k,
+                                   a.stride_chain, (const T *)a.G, vo);
+            }
             if (a.counter) hipLaunchKernelGGL(g2_count, dim3(1), dim3(64), 0, st, gs, nch, a.counter);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }

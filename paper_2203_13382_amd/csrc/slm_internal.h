@@ -17,6 +17,8 @@ struct LevelInfo {
     size_t V = 0;           // [(N+1)][S] T, l >= 1: iterate
     size_t G = 0;           // [(N+1)][S] T, l >= 1: right-hand side
     size_t C = 0;           // [(N/m+1)][S] T: C-point buffer (not on the coarsest level)
+    size_t idx_end = 0;     // adjoint: [N][S] int, end of each stencil cell's source list
+    size_t idx_perm = 0;    // adjoint: [N][S] int, sources ordered by stencil cell
 };
 
 // Per-system Givens state of the batched 2D GMRES.
@@ -43,6 +45,12 @@ struct slm_plan {
     // 2D: chains per launch batch, ping-pong slices and batched-GMRES state
     int cap2 = 0, capg = 0, nb2 = 0;
     size_t w2 = 0, g2b = 0, g2v = 0, g2w = 0, g2s = 0, g2p = 0, part2 = 0;
+    // adjoint: reverse-time mode of the chain kernels, inverse index ready,
+    // checkpoint recomputation (gcap chains at a time) and gradient sums
+    int adj_mode = 0;
+    bool adj_ready = false;
+    int gcap = 0, nq = 0;
+    size_t lamC = 0, gU = 0, gL = 0, gacc = 0, gout = 0;
     size_t ws_bytes = 0;
     char *ws = nullptr;
     bool ready = false;
@@ -74,6 +82,8 @@ struct ChainArgs {
     double rtol;
     unsigned long long *counter;
     int nsmall;              // |displacement| bound < nx - p - 1 (cheap wrap)
+    int adj;                 // 1: adjoint system in reverse time (transposed steps)
+    int Nl;                  // level steps; step n of the adjoint uses forward step Nl-1-n
 };
 
 // launchers (slm_chain1d.hip / slm_setup.hip / slm_misc.hip)
@@ -89,6 +99,17 @@ hipError_t launch_axpy_slices(void *dst, long long dst_stride, const void *src, 
                               int count, int S, int elem, int assign, hipStream_t st);
 hipError_t launch_copy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
                               int count, int S, int elem, hipStream_t st);
+// adjoint (slm_adjoint.hip)
+hipError_t launch_adj_index(const slm_plan &P, int level, hipStream_t st);
+hipError_t launch_stepT(const slm_plan &P, int level, int nch, const double *src, long long src_stride, double *dst,
+                        long long dst_stride, long long n_first, int stride, int rev, const double *G, double *Vout,
+                        hipStream_t st);
+hipError_t launch_step_fwd(const slm_plan &P, int nch, const double *src, long long src_stride, double *dst,
+                           long long dst_stride, long long n_first, int stride, hipStream_t st);
+hipError_t launch_grad(const slm_plan &P, int nch, const double *U, long long u_stride, const double *lam,
+                       long long lam_stride, long long n_first, int stride, double *gacc, hipStream_t st);
+hipError_t launch_grad_reduce(const slm_plan &P, int nchains, double *out, hipStream_t st);
+hipError_t launch_fill0(double *p, long long n, hipStream_t st);
 
 // message returned by slm_last_error(NULL) (slm_plan.hip)
 void slm_set_error(const std::string &msg);

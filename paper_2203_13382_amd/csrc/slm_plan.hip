@@ -67,19 +67,21 @@ ChainArgs base_args(const slm_plan &P, int level)
     a.rtol = P.d.gmres_rtol;
     a.counter = (unsigned long long *)ws_at(P, P.counter);
     a.nsmall = level == 0 && disp_bound(P) + P.d.p + 8 < P.d.nx ? 1 : 0;
+    a.adj = P.adj_mode;
+    a.Nl = P.lv[level].N;
     return a;
 }
 
 // Device sum of the residual partial sums of a sweep over nc chains.
 hipError_t sum_norm(const slm_plan &P, int nc, double *out, hipStream_t st)
 {
-    if (P.d.dim == 2) return launch_sum_partials((const double *)ws_at(P, P.part2), nc * P.nb2, out, st);
+    if (P.d.dim == 2 || P.adj_mode) return launch_sum_partials((const double *)ws_at(P, P.part2), nc * P.nb2, out, st);
     return launch_sum_partials((const double *)ws_at(P, P.partial), nc, out, st);
 }
 
 hipError_t chain(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
 {
-    return P.d.dim == 1 ? launch_chain_1d(P, level, nchains, a, st) : launch_chain_2d(P, level, nchains, a, st);
+    return P.d.dim == 1 && !a.adj ? launch_chain_1d(P, level, nchains, a, st) : launch_chain_2d(P, level, nchains, a, st);
 }
 
 struct Solver {
@@ -150,6 +152,113 @@ struct Solver {
     }
 };
 
+
+// Linear MGRIT driver shared by slm_solve (d_u: every time point in and
+// out), slm_solve_cpoints (d_c: C-points in and out) and the adjoint
+// (P.adj_mode: the reverse-time adjoint system, d_c receives its C-values).
+int solve_core(slm_plan *P, const void *d_u0, void *d_u, void *d_c, slm_stats *stats, double *h_hist, int hist_cap,
+               hipStream_t st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    const int S = P->S;
+    const size_t sl = (size_t)S * P->elem;
+    char *u = (char *)d_u;
+    slm_stats s;
+    std::memset(&s, 0, sizeof(s));
+    s.n_levels = P->L;
+    HIPCHK(hipMemsetAsync(ws_at(*P, P->counter), 0, 2 * sizeof(unsigned long long), st));
+    Solver sv{*P, st};
+    if (P->L == 1) {                        // no coarsening: sequential stepping
+        int rc = slm_step(P, d_u0, d_u, 1, st);
+        if (rc) return rc;
+        sv.updates += (long long)P->d.nt * S;
+        s.status = SLM_OK;
+    } else {
+        const int m0 = P->lv[0].m, nc0 = P->d.nt / m0;
+        const bool fcf = P->d.relax == SLM_RELAX_FCF;
+        char *Ca = ws_at(*P, P->lv[0].C), *Cb = ws_at(*P, P->C0b);
+        if (u) HIPCHK(launch_copy_slices(Ca, S, u, (long long)m0 * S, nc0 + 1, S, P->elem, st));
+        else HIPCHK(launch_copy_slices(Ca, S, d_c, S, nc0 + 1, S, P->elem, st));
+        HIPCHK(launch_copy_slices(Ca, S, d_u0, S, 1, S, P->elem, st));
+        double *dn = (double *)ws_at(*P, P->norm);
+        double rho0 = 0.0;
+        int stag = 0;
+        double prev = 0.0;
+        for (int k = 0;; ++k) {
+            char *Cc = Ca;                 // C-values after pre-relaxation
+            if (fcf) {
+                ChainArgs a = base_args(*P, 0);
+                a.nsteps = m0;
+                a.Cin = Ca;
+                a.Cout = Cb;
+                HIPCHK(chain(*P, 0, nc0, a, st));
+                sv.updates += (long long)P->d.nt * S;
+                Cc = Cb;
+            }
+            {
+                ChainArgs a = base_args(*P, 0);
+                a.nsteps = m0;
+                a.Cin = Cc;
+                a.Cref = Cc;
+                a.R = ws_at(*P, P->lv[1].G);
+                a.partial = (double *)ws_at(*P, P->partial);
+                HIPCHK(chain(*P, 0, nc0, a, st));
+                sv.updates += (long long)P->d.nt * S;
+            }
+            HIPCHK(sum_norm(*P, nc0, dn, st));
+            double v = 0.0;
+            HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double rho = std::sqrt(v);
+            if (h_hist && k < hist_cap) h_hist[k] = rho;
+            if (k == 0) rho0 = rho;
+            s.iterations = k + 1;
+            s.rho_final = rho;
+            const double thr = P->d.tol_mode == SLM_TOL_REL ? P->d.tol * rho0 : P->d.tol;
+            bool stop = true;
+            if (rho < thr || rho == 0.0) s.status = SLM_OK;
+            else if (!std::isfinite(rho) || rho > 1e3 * rho0) s.status = SLM_DIVERGED;
+            else if (P->d.precision == SLM_FP32_BULK && k > 0 && (stag = rho > 0.95 * prev ? stag + 1 : 0) >= 3)
+                s.status = SLM_STAGNATED;
+            else if (k >= P->d.max_iter) s.status = SLM_NOT_CONVERGED;
+            else stop = false;
+            prev = rho;
+            if (stop) {
+                Ca = Cc;
+                break;
+            }
+            int rc = sv.cycle(1);
+            if (rc) return rc;
+            HIPCHK(launch_axpy_slices(Cc + sl, S, ws_at(*P, P->lv[1].V) + sl, S, nc0, S, P->elem, 0, st));
+            if (fcf) std::swap(Ca, Cb);     // the corrected C-values become the next cycle's start
+        }
+        s.rho0 = rho0;
+        if (u) {
+            // output: F-relaxation from the final C-values writes every point
+            ChainArgs a = base_args(*P, 0);
+            a.nsteps = m0 - 1;
+            a.Cin = Ca;
+            a.Vout = u;
+            a.write_start = 1;
+            a.write_last = 1;
+            HIPCHK(chain(*P, 0, nc0, a, st));
+            HIPCHK(launch_copy_slices(u + (size_t)P->d.nt * sl, S, Ca + (size_t)nc0 * sl, S, 1, S, P->elem, st));
+            sv.updates += (long long)(P->d.nt - nc0) * S;
+        } else {
+            HIPCHK(launch_copy_slices(d_c, S, Ca, S, nc0 + 1, S, P->elem, st));
+        }
+    }
+    unsigned long long cnt[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(cnt, ws_at(*P, P->counter), sizeof(cnt), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s.gmres_solves = (long long)cnt[0];
+    s.gmres_iters = (long long)cnt[1];
+    s.point_updates = sv.updates;
+    s.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = s;
+    return s.status;
+}
+
 }  // namespace
 
 void slm_set_error(const std::string &msg) { g_err = msg; }
@@ -199,6 +308,11 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
     if (d->tol_mode != SLM_TOL_ABS && d->tol_mode != SLM_TOL_REL) return fail(nullptr, SLM_EINVAL, "bad tol_mode");
     if (d->max_iter < 1) return fail(nullptr, SLM_EINVAL, "max_iter >= 1 required");
     if (d->precision != SLM_FP64 && d->precision != SLM_FP32_BULK) return fail(nullptr, SLM_EINVAL, "bad precision");
+    if (d->adjoint != 0 && d->adjoint != 1) return fail(nullptr, SLM_EINVAL, "adjoint must be 0 or 1");
+    if (d->adjoint && (d->precision != SLM_FP64 || d->p % 2 == 0))
+        return fail(nullptr, SLM_EUNSUPPORTED, "the adjoint needs SLM_FP64 and odd p");
+    if (d->adjoint && d->n_alpha + (d->dim == 2 ? d->n_beta : 0) > 16)
+        return fail(nullptr, SLM_EUNSUPPORTED, "the adjoint supports at most 16 wave-speed coefficients");
 
     slm_plan *P = new (std::nothrow) slm_plan();
     if (!P) return fail(nullptr, SLM_EINVAL, "out of host memory");
@@ -231,6 +345,11 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
         delete P;
         return fail(nullptr, SLM_EUNSUPPORTED, "MGRIT with the modified coarse operator needs odd p");
     }
+    if (d->adjoint && P->L < 2) {
+        delete P;
+        return fail(nullptr, SLM_EUNSUPPORTED, "the adjoint needs at least two levels");
+    }
+    P->nq = d->adjoint ? d->n_alpha + (d->dim == 2 ? d->n_beta : 0) : 0;
 
     // workspace layout
     const size_t S = P->S, el = P->elem, dim = d->dim;
@@ -256,7 +375,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
             if ((size_t)(L.N / L.m) > maxc) maxc = L.N / L.m;
         }
     }
-    if (d->dim == 2) {
+    if (d->dim == 2 || d->adjoint) {
         size_t cap2 = 1, capg = 1;
         for (int l = 0; l < P->L; ++l) {
             const size_t nc = P->lv[l].m ? (size_t)P->lv[l].N / P->lv[l].m : 1;
@@ -275,6 +394,19 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
             P->g2s = take(capg * sizeof(Gs2));
             P->g2p = take((3 * capg * (size_t)P->nb2 * SLM_NPART2 + capg * (SLM_KMAX + 1)) * sizeof(double));
         }
+    }
+    if (d->adjoint) {
+        const size_t nc0 = (size_t)d->nt / L0.m;
+        for (int l = 0; l < P->L; ++l) {
+            P->lv[l].idx_end = take((size_t)P->lv[l].N * S * sizeof(int));
+            P->lv[l].idx_perm = take((size_t)P->lv[l].N * S * sizeof(int));
+        }
+        P->gcap = (int)(nc0 < 64 ? nc0 : 64);
+        P->lamC = take((nc0 + 1) * S * sizeof(double));
+        P->gU = take((size_t)P->gcap * L0.m * S * sizeof(double));
+        P->gL = take(2 * (size_t)P->gcap * S * sizeof(double));
+        P->gacc = take(nc0 * (size_t)P->nb2 * 16 * sizeof(double));
+        P->gout = take(16 * sizeof(double));
     }
     P->partial = take(maxc * sizeof(double));
     P->norm = take(sizeof(double));
@@ -423,100 +555,74 @@ int slm_solve(slm_plan *P, const void *d_u0, void *d_u, slm_stats *stats, double
     if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
     if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
     if (!d_u0 || !d_u) return fail(P, SLM_EINVAL, "NULL pointer");
-    const auto t0 = std::chrono::steady_clock::now();
+    return solve_core(P, d_u0, d_u, nullptr, stats, h_hist, hist_cap, (hipStream_t)stream);
+}
+
+int slm_solve_cpoints(slm_plan *P, const void *d_u0, void *d_c, slm_stats *stats, double *h_hist, int hist_cap,
+                      void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (!d_u0 || !d_c) return fail(P, SLM_EINVAL, "NULL pointer");
+    if (P->L < 2) return fail(P, SLM_EUNSUPPORTED, "C-point checkpoints need at least two levels");
+    return solve_core(P, d_u0, nullptr, d_c, stats, h_hist, hist_cap, (hipStream_t)stream);
+}
+
+int slm_adjoint(slm_plan *P, const void *d_c, const void *d_lamT, void *d_grad_u0, double *h_grad_theta,
+                slm_stats *stats, double *h_hist, int hist_cap, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (!P->d.adjoint) return fail(P, SLM_EUNSUPPORTED, "plan was created without desc.adjoint = 1");
+    if (!d_c || !d_lamT || !d_grad_u0) return fail(P, SLM_EINVAL, "NULL pointer");
     hipStream_t st = (hipStream_t)stream;
-    const int S = P->S;
-    const size_t sl = (size_t)S * P->elem;
-    char *u = (char *)d_u;
-    slm_stats s;
-    std::memset(&s, 0, sizeof(s));
-    s.n_levels = P->L;
-    HIPCHK(hipMemsetAsync(ws_at(*P, P->counter), 0, 2 * sizeof(unsigned long long), st));
-    Solver sv{*P, st};
-    if (P->L == 1) {                        // no coarsening: sequential stepping
-        int rc = slm_step(P, d_u0, d_u, 1, stream);
-        if (rc) return rc;
-        sv.updates += (long long)P->d.nt * S;
-        s.status = SLM_OK;
-    } else {
-        const int m0 = P->lv[0].m, nc0 = P->d.nt / m0;
-        const bool fcf = P->d.relax == SLM_RELAX_FCF;
-        char *Ca = ws_at(*P, P->lv[0].C), *Cb = ws_at(*P, P->C0b);
-        HIPCHK(launch_copy_slices(Ca, S, u, (long long)m0 * S, nc0 + 1, S, P->elem, st));
-        HIPCHK(launch_copy_slices(Ca, S, d_u0, S, 1, S, P->elem, st));
-        double *dn = (double *)ws_at(*P, P->norm);
-        double rho0 = 0.0;
-        int stag = 0;
-        double prev = 0.0;
-        for (int k = 0;; ++k) {
-            char *Cc = Ca;                 // C-values after pre-relaxation
-            if (fcf) {
-                ChainArgs a = base_args(*P, 0);
-                a.nsteps = m0;
-                a.Cin = Ca;
-                a.Cout = Cb;
-                HIPCHK(chain(*P, 0, nc0, a, st));
-                sv.updates += (long long)P->d.nt * S;
-                Cc = Cb;
-            }
-            {
-                ChainArgs a = base_args(*P, 0);
-                a.nsteps = m0;
-                a.Cin = Cc;
-                a.Cref = Cc;
-                a.R = ws_at(*P, P->lv[1].G);
-                a.partial = (double *)ws_at(*P, P->partial);
-                HIPCHK(chain(*P, 0, nc0, a, st));
-                sv.updates += (long long)P->d.nt * S;
-            }
-            HIPCHK(sum_norm(*P, nc0, dn, st));
-            double v = 0.0;
-            HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            const double rho = std::sqrt(v);
-            if (h_hist && k < hist_cap) h_hist[k] = rho;
-            if (k == 0) rho0 = rho;
-            s.iterations = k + 1;
-            s.rho_final = rho;
-            const double thr = P->d.tol_mode == SLM_TOL_REL ? P->d.tol * rho0 : P->d.tol;
-            bool stop = true;
-            if (rho < thr || rho == 0.0) s.status = SLM_OK;
-            else if (!std::isfinite(rho) || rho > 1e3 * rho0) s.status = SLM_DIVERGED;
-            else if (P->d.precision == SLM_FP32_BULK && k > 0 && (stag = rho > 0.95 * prev ? stag + 1 : 0) >= 3)
-                s.status = SLM_STAGNATED;
-            else if (k >= P->d.max_iter) s.status = SLM_NOT_CONVERGED;
-            else stop = false;
-            prev = rho;
-            if (stop) {
-                Ca = Cc;
-                break;
-            }
-            int rc = sv.cycle(1);
-            if (rc) return rc;
-            HIPCHK(launch_axpy_slices(Cc + sl, S, ws_at(*P, P->lv[1].V) + sl, S, nc0, S, P->elem, 0, st));
-            if (fcf) std::swap(Ca, Cb);     // the corrected C-values become the next cycle's start
-        }
-        s.rho0 = rho0;
-        // output: F-relaxation from the final C-values writes every point
-        ChainArgs a = base_args(*P, 0);
-        a.nsteps = m0 - 1;
-        a.Cin = Ca;
-        a.Vout = u;
-        a.write_start = 1;
-        a.write_last = 1;
-        HIPCHK(chain(*P, 0, nc0, a, st));
-        HIPCHK(launch_copy_slices(u + (size_t)P->d.nt * sl, S, Ca + (size_t)nc0 * sl, S, 1, S, P->elem, st));
-        sv.updates += (long long)(P->d.nt - nc0) * S;
+    const long long S = P->S;
+    const int m0 = P->lv[0].m, nc0 = P->d.nt / m0;
+    // inverse stencil index of every level (once per setup)
+    if (!P->adj_ready) {
+        for (int l = 0; l < P->L; ++l) HIPCHK(launch_adj_index(*P, l, st));
+        P->adj_ready = true;
     }
-    unsigned long long cnt[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(cnt, ws_at(*P, P->counter), sizeof(cnt), hipMemcpyDeviceToHost, st));
+    // 1. lambda at the C-points: MGRIT on the adjoint system in reverse time,
+    //    from a zero initial iterate (C-point 0 of reverse time = lambda_nt)
+    double *lamC = (double *)ws_at(*P, P->lamC);
+    HIPCHK(launch_fill0(lamC, (nc0 + 1) * S, st));
+    P->adj_mode = 1;
+    const int rc = solve_core(P, d_lamT, nullptr, lamC, stats, h_hist, hist_cap, st);
+    P->adj_mode = 0;
+    if (rc < 0) return rc;
+    // 2. per coarse interval: recompute u_n from the checkpoint, sweep lambda
+    //    back through the interval and accumulate the gradient
+    double *gacc = (double *)ws_at(*P, P->gacc);
+    HIPCHK(launch_fill0(gacc, (long long)nc0 * P->nb2 * 16, st));
+    double *U = (double *)ws_at(*P, P->gU), *Lb = (double *)ws_at(*P, P->gL);
+    const double *C = (const double *)d_c;
+    for (int c0 = 0; c0 < nc0; c0 += P->gcap) {
+        const int nch = nc0 - c0 < P->gcap ? nc0 - c0 : P->gcap;
+        const long long us = (long long)m0 * S;
+        HIPCHK(launch_copy_slices(U, us, C + (long long)c0 * S, S, nch, (int)S, 8, st));
+        for (int k = 0; k + 1 < m0; ++k)
+            HIPCHK(launch_step_fwd(*P, nch, U + k * S, us, U + (k + 1) * S, us, (long long)c0 * m0 + k, m0, st));
+        // lambda at forward time (c0+c+1) m0 is reverse-time C-point nc0-(c0+c+1)
+        for (int c = 0; c < nch; ++c)
+            HIPCHK(launch_copy_slices(Lb + (long long)c * S, S, lamC + (long long)(nc0 - (c0 + c + 1)) * S, S, 1,
+                                      (int)S, 8, st));
+        double *cur = Lb, *nxt = Lb + (long long)P->gcap * S;
+        for (int k = m0 - 1; k >= 0; --k) {
+            HIPCHK(launch_grad(*P, nch, U + k * S, us, cur, S, (long long)c0 * m0 + k, m0, gacc, st));
+            HIPCHK(launch_stepT(*P, 0, nch, cur, S, nxt, S, (long long)c0 * m0 + k, m0, 0, nullptr, nullptr, st));
+            std::swap(cur, nxt);
+        }
+        if (c0 == 0) HIPCHK(launch_copy_slices(d_grad_u0, S, cur, S, 1, (int)S, 8, st));
+    }
+    double *gout = (double *)ws_at(*P, P->gout);
+    HIPCHK(launch_grad_reduce(*P, nc0, gout, st));
+    double g[16];
+    HIPCHK(hipMemcpyAsync(g, gout, sizeof(g), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    s.gmres_solves = (long long)cnt[0];
-    s.gmres_iters = (long long)cnt[1];
-    s.point_updates = sv.updates;
-    s.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (stats) *stats = s;
-    return s.status;
+    if (h_grad_theta)
+        for (int q = 0; q < P->nq; ++q) h_grad_theta[q] = g[q];
+    return rc;
 }
 
 }  // extern "C"

@@ -28,14 +28,15 @@ class Plan:
     """One problem (``Problem``), solver settings (``Solver``) and precision
     ("fp64" or "fp32": FP32 bulk with FP64 tracing and norms)."""
 
-    def __init__(self, problem, solver, precision="fp64", device="cuda"):
+    def __init__(self, problem, solver, precision="fp64", device="cuda", adjoint=False):
         if torch is None:
             raise N.NativeError("torch is required for device memory")
         self.pr, self.sv, self.precision = problem, solver, precision
+        self.adjoint_enabled = bool(adjoint)
         self.device = torch.device(device)
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.S = problem.nx if problem.dim == 1 else problem.nx * problem.nx
-        desc, self._keep = N.make_desc(problem, solver, precision)
+        desc, self._keep = N.make_desc(problem, solver, precision, adjoint)
         self._desc = desc
         h = C.c_void_p()
         N.check(N.lib().slm_plan_create(C.byref(desc), C.byref(h)))
@@ -148,6 +149,37 @@ class Plan:
         stats = _stats_dict(st)
         nh = min(hist_cap, st.iterations)
         return stats, np.array([hist[i] for i in range(nh)])
+
+    @property
+    def n_cpoints(self):
+        return self.pr.nt // self.m[0] + 1
+
+    def solve_cpoints(self, u0, c, hist_cap=512, stream=None):
+        """MGRIT keeping only the C-points: ``c`` ([nt/m0+1][S] device tensor)
+        holds the initial iterate on entry and the converged C-values on
+        exit.  Returns (stats, history)."""
+        assert c.dtype == self.dtype and c.is_contiguous() and c.numel() == self.n_cpoints * self.S
+        u0 = self._dev(u0).reshape(self.S)
+        st = N.Stats()
+        hist = (C.c_double * hist_cap)()
+        N.check(N.lib().slm_solve_cpoints(self.h, _ptr(u0), _ptr(c), C.byref(st), hist, hist_cap,
+                                          _stream(stream)), self.h)
+        return _stats_dict(st), np.array([hist[i] for i in range(min(hist_cap, st.iterations))])
+
+    def adjoint(self, c, lamT, hist_cap=512, stream=None):
+        """Gradient of a final-time misfit with dL/du_nt = ``lamT``, from the
+        C-point checkpoints ``c``.  Returns (dL/du0 device tensor, dL/dtheta
+        numpy array [n_alpha + n_beta], stats, history)."""
+        lamT = self._dev(lamT).reshape(self.S)
+        g0 = torch.empty(self.S, dtype=torch.float64, device=self.device)
+        nq = len(self.pr.alpha) + (len(self.pr.beta or []) if self.pr.dim == 2 else 0)
+        gth = (C.c_double * max(1, nq))()
+        st = N.Stats()
+        hist = (C.c_double * hist_cap)()
+        N.check(N.lib().slm_adjoint(self.h, _ptr(c), _ptr(lamT), _ptr(g0), gth, C.byref(st), hist, hist_cap,
+                                    _stream(stream)), self.h)
+        return (g0, np.array([gth[q] for q in range(nq)]), _stats_dict(st),
+                np.array([hist[i] for i in range(min(hist_cap, st.iterations))]))
 
 
 def _stats_dict(st):

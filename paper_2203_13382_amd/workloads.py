@@ -134,3 +134,25 @@ def batch_config(n: int = 64, seed: int = 4, cfl: float = 0.85, precision: str =
         sk = {k: v for k, v in over.items() if hasattr(sv, k)}
         out.append((replace(pr, **pk), replace(sv, **sk)))
     return out, precision
+
+
+def adjoint_config(seed: int = 5, **over):
+    """The adjoint workload: 2D, nx = ny = 256, nt = 2048, dt = 2h, p = r = 3,
+    m = 4 down to <= 16 points, FCF, FP64, field_cfg5(theta).  The misfit
+    target comes from theta_true = (1, 0, 1, 0) + 0.05 N(0,1); the gradient
+    is taken at theta = (1, 0, 1, 0) + 0.02 N(0,1) (generic coefficients:
+    at exactly (1, 0, 1, 0) some departure points sit on mesh nodes, where
+    the interpolant's slope jumps).  Returns (Problem at theta, Solver,
+    theta, theta_true)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    base = np.array([1.0, 0.0, 1.0, 0.0])
+    theta_true = base + 0.05 * rng.standard_normal(4)
+    theta = base + 0.02 * rng.standard_normal(4)
+    nx = over.get("nx", 256)
+    nt = over.get("nt", 2048)
+    a, b = field_cfg5(tuple(theta))
+    pr = Problem(2, nx, nt, 2.0 * 2.0 / nx, 3, 3, a, b)
+    sv = Solver(m=[4], coarsest_max_points=16, relax="FCF", gmres_kmax=10, gmres_rtol=1e-2,
+                tol=over.get("tol", 1e-10), tol_mode="rel", max_iter=100)
+    return pr, sv, theta, theta_true
