@@ -44,8 +44,10 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the level-0 F+C sweep kernel and a 1 GiB device copy (for counter runs)")
-    ap.add_argument("--workload", choices=["1d", "batch"], default="1d",
-                    help="1d: the single 1D problem (default line); batch: 64 drawn 1D problems solved together")
+    ap.add_argument("--workload", choices=["1d", "batch", "adjoint", "2d"], default="1d",
+                    help="1d: the single 1D problem (default line); batch: 64 drawn 1D problems solved together; "
+                         "adjoint: gradient of a final-time misfit for the 2D 256^2 problem; "
+                         "2d: the 2D 512^2 FP32-bulk problem")
     return ap.parse_args()
 
 
@@ -143,6 +145,142 @@ def kernel_only(args):
                       "copy_bytes_each_way": src.numel() * 8, "copy_ms": cms}))
 
 
+def adjoint_bench(args):
+    """2D adjoint workload (256^2, nt = 2048, dt = 2h, p = r = 3, m = 4 to
+    <= 16 points, FCF, FP64): one step = plan setup + forward MGRIT keeping
+    the C-point checkpoints + the adjoint (inverse stencil index, reverse-time
+    adjoint MGRIT, F-point recomputation and gradient accumulation).  The
+    sequential baseline is GPU sequential stepping of the forward problem."""
+    import ctypes as C
+    import torch
+    from paper_2203_13382_amd import Plan
+    from paper_2203_13382_amd import _native as N
+    from paper_2203_13382_amd import inputs as I
+    from paper_2203_13382_amd import workloads as W
+    from paper_2203_13382_amd.autograd import with_theta
+    pr, sv, theta, theta_true = W.adjoint_config()
+    stream = torch.cuda.current_stream()
+    u0 = torch.from_numpy(I.initial_condition(pr, 0)).cuda()
+    seq_plan = Plan(with_theta(pr, theta_true), W.Solver(m=[2], max_levels=1), "fp64").setup()
+    u_obs = torch.empty(pr.S, dtype=torch.float64, device="cuda")
+    N.check(N.lib().slm_step(seq_plan.h, C.c_void_p(u0.data_ptr()), C.c_void_p(u_obs.data_ptr()), 0,
+                             C.c_void_p(stream.cuda_stream)), seq_plan.h)
+    plan = Plan(pr, sv, "fp64", adjoint=True)
+    m0 = sv.m[0]
+    c_init = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, m0, 1)[::m0].copy()).cuda()
+    c = torch.empty_like(c_init)
+    r = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def one_step():
+        ev[0].record(stream)
+        plan.setup()
+        c.copy_(c_init)
+        r["f"], _ = plan.solve_cpoints(u0, c)
+        ev[1].record(stream)
+        r["g0"], r["gth"], r["a"], _ = plan.adjoint(c, c[-1] - u_obs)
+        ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    tot, fwd, adj = [], [], []
+    for _ in range(args.steps):
+        one_step()
+        torch.cuda.synchronize()
+        tot.append(ev[0].elapsed_time(ev[2]))
+        fwd.append(ev[0].elapsed_time(ev[1]))
+        adj.append(ev[1].elapsed_time(ev[2]))
+    ms = float(np.mean(tot))
+    upd = r["f"]["point_updates"] + r["a"]["point_updates"]
+    pl1 = Plan(pr, W.Solver(m=[2], max_levels=1), "fp64")
+    useq = torch.empty(pr.S, dtype=torch.float64, device="cuda")
+
+    def seq_step():
+        pl1.setup()
+        N.check(N.lib().slm_step(pl1.h, C.c_void_p(u0.data_ptr()), C.c_void_p(useq.data_ptr()), 0,
+                                 C.c_void_p(stream.cuda_stream)), pl1.h)
+    seq_ms = timed(torch, seq_step, max(1, args.steps))
+    out = {
+        "metric": METRIC, "value": upd / (ms * 1e-3), "unit": "point-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"adjoint of 2D advection, nx=ny={pr.nx}, nt={pr.nt}, dt=2h, p=r=3, m=4 to <=16 "
+                               f"points, FCF, FP64, loss 1/2||u(T)-u_obs||^2, gradient wrt u0 and 4 wave-speed "
+                               f"coefficients, C-point checkpoints", "precision": "fp64"},
+        "adjoint": {"time_to_gradient_ms": ms, "forward_ms": float(np.mean(fwd)), "adjoint_ms": float(np.mean(adj)),
+                    "forward_iterations": r["f"]["iterations"], "adjoint_iterations": r["a"]["iterations"],
+                    "point_updates": upd, "grad_theta": [float(v) for v in r["gth"]],
+                    "grad_u0_norm": float(r["g0"].norm())},
+        "seq": {"forward_ms": seq_ms},
+        "forward_speedup_vs_seq": seq_ms / float(np.mean(fwd)),
+    }
+    print(json.dumps(out))
+
+
+def twod_bench(args):
+    """2D workload: nx = ny = 512, nt = 4096, dt = 2h, p = r = 5, m = 8 to
+    <= 16 points, FCF, FP32 bulk (FP64 tracing, sigma and norms), relative
+    tolerance 1e-6.  One step = setup + MGRIT + final F-relaxation; beside it
+    GPU sequential stepping and the FP32-vs-FP64 error at the final time."""
+    import ctypes as C
+    import torch
+    from paper_2203_13382_amd import Plan
+    from paper_2203_13382_amd import _native as N
+    from paper_2203_13382_amd import inputs as I
+    from paper_2203_13382_amd import workloads as W
+    pr, sv, prec = W.config(3)
+    stream = torch.cuda.current_stream()
+    u0 = torch.from_numpy(I.initial_condition(pr, 0)).cuda()
+    ui = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 1).astype(np.float32)).cuda()
+    plan = Plan(pr, sv, prec)
+    u = torch.empty_like(ui)
+    u032 = u0.float()
+    r = {}
+
+    def one_step():
+        plan.setup()
+        u.copy_(ui)
+        r["st"], _ = plan.solve(u032, u)
+
+    for _ in range(args.warmup):
+        one_step()
+    ms = timed(torch, one_step, max(1, args.steps), warm=0)
+    st = r["st"]
+    seq = Plan(pr, W.Solver(m=[2], max_levels=1), "fp64")
+    useq = torch.empty(pr.S, dtype=torch.float64, device="cuda")
+
+    def seq_step():
+        seq.setup()
+        N.check(N.lib().slm_step(seq.h, C.c_void_p(u0.data_ptr()), C.c_void_p(useq.data_ptr()), 0,
+                                 C.c_void_p(stream.cuda_stream)), seq.h)
+    seq_ms = timed(torch, seq_step, max(1, args.steps))
+    seq32 = Plan(pr, W.Solver(m=[2], max_levels=1), "fp32")
+    useq32 = torch.empty(pr.S, dtype=torch.float32, device="cuda")
+
+    def seq32_step():
+        seq32.setup()
+        N.check(N.lib().slm_step(seq32.h, C.c_void_p(u032.data_ptr()), C.c_void_p(useq32.data_ptr()), 0,
+                                 C.c_void_p(stream.cuda_stream)), seq32.h)
+    seq32_ms = timed(torch, seq32_step, max(1, args.steps))
+    err = float((u[-1].double() - useq).abs().max() / useq.abs().max())
+    out = {
+        "metric": METRIC, "value": st["point_updates"] / (ms * 1e-3), "unit": "point-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"2D advection alpha=(cos(pi y)cos(pi t), sin(pi x)), nx=ny={pr.nx}, nt={pr.nt}, "
+                               f"dt=2h, p=r=5 tensor product, m=8 to <=16 points, FCF, FP32 bulk + FP64 "
+                               f"tracing/norms, rel. tol 1e-6", "precision": prec},
+        "mgrit": {"time_to_tol_ms": ms, "iterations": st["iterations"], "status": st["status"],
+                  "rho_final_over_rho0": st["rho_final"] / st["rho0"], "point_updates": st["point_updates"],
+                  "gmres_solves": st["gmres_solves"], "gmres_iters": st["gmres_iters"],
+                  "max_rel_err_vs_fp64_seq_at_T": err},
+        "seq": {"fp64_ms": seq_ms, "fp32_ms": seq32_ms},
+        "speedup_vs_fp32_seq": seq32_ms / ms,
+    }
+    print(json.dumps(out))
+
+
 def measured_traffic():
     """HBM bytes per launch of the level-0 sweep from the committed counter
     summary, or None once the kernel sources (device code of the sweep and
@@ -208,6 +346,10 @@ def main():
         return kernel_only(args)
     if args.workload == "batch":
         return batch_bench(args)
+    if args.workload == "adjoint":
+        return adjoint_bench(args)
+    if args.workload == "2d":
+        return twod_bench(args)
     dev = torch.device("cuda")
 
     pr, sv, _ = W.config(2)

@@ -255,7 +255,7 @@ struct Builder {
     // of their slice, the shape the per-level kernel would use.
     static void fine_shape(int nx, int &block, int &ept)
     {
-        block = nx >= SLM_MAXB ? SLM_MAXB : (nx + 63) / 64 * 64;
+        block = fine_block(nx, 1 << 30);   // a batch sweep has many items
         const int e = (nx + block - 1) / block;
         ept = e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : 8;
     }

@@ -49,7 +49,7 @@ hipError_t launch(K kern, int nchains, int block, size_t lds, const ChainArgs &a
 template <typename T, typename TD, int P, bool DBUF>
 hipError_t fine_ept(const ChainArgs &a, int nchains, hipStream_t st)
 {
-    const int block = a.nx >= SLM_MAXB ? SLM_MAXB : ((a.nx + 63) / 64) * 64;
+    const int block = fine_block(a.nx, nchains);
     const int ept = (a.nx + block - 1) / block;
     const size_t lds = (((size_t)(DBUF ? 2 : 1) * a.nx * sizeof(T) + 15) & ~size_t(15)) +
                        SLM_RED_DOUBLES * sizeof(double);

@@ -124,14 +124,6 @@ __global__ void __launch_bounds__(TPB) start2d_kernel(const T *__restrict__ Cin,
 // ------------------------------------------------------------ batched GMRES
 // (per-system Givens state Gs2 is declared in slm_internal.h)
 
-// Fixed-order sum of the nb block partials of slot q for system c.
-__device__ __forceinline__ double part_sum(const double *part, int c, int nb, int q)
-{
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[((long long)c * nb + b) * NPART + q];
-    return s;
-}
-
 template <int NV>
 __device__ __forceinline__ void write_parts(double (&v)[NV], double *red, double *part, int c)
 {
@@ -153,13 +145,36 @@ __global__ void __launch_bounds__(TPB) g2_norm0(const T *__restrict__ b, long lo
     write_parts<1>(v, red, part, c);
 }
 
-// beta, V0 = b / beta (every block recomputes beta from the partials)
+// Fixed-order reduction of the per-block partials of every system: one
+// workgroup per system sums its nb blocks' slots q < nv (each thread a
+// strided subset, then a deterministic workgroup tree) into out[c][q].
+// Systems already converged are skipped when gs is given.
+__global__ void __launch_bounds__(TPB) g2_sum(const double *__restrict__ part, int nb, int nv, const Gs2 *gs,
+                                              double *__restrict__ out)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.x;
+    if (gs && gs[c].done) return;
+    double v[SLM_KMAX + 1];
+#pragma unroll
+    for (int q = 0; q <= SLM_KMAX; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += TPB) {
+        const double *pp = part + ((long long)c * nb + b) * NPART;
+#pragma unroll
+        for (int q = 0; q <= SLM_KMAX; ++q)
+            if (q < nv) v[q] += pp[q];
+    }
+    block_sum<SLM_KMAX + 1>(v, red, 0);
+    if (threadIdx.x < nv) out[(long long)c * NPART + threadIdx.x] = v[threadIdx.x];
+}
+
+// beta = ||b|| from the reduced b.b, V0 = b / beta
 template <typename T>
-__global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long long S, const double *part, int nb,
-                                                 T *V, Gs2 *gs, int kmax)
+__global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long long S, const double *bb, T *V,
+                                                 Gs2 *gs, int kmax)
 {
     const int c = blockIdx.y;
-    const double beta = sqrt(part_sum(part, c, nb, 0));
+    const double beta = sqrt(bb[(long long)c * NPART]);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         Gs2 &g = gs[c];
         g.beta = beta;
@@ -226,23 +241,19 @@ __global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__r
     if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
-// w -= sum_i h_i V_i with h from the partials; then partials of V_i . w (i <= j)
-// when `dots`, or of w . w otherwise.  The h of pass 1 are kept in hkeep.
+// w -= sum_i h_i V_i with the reduced h (i <= j); then partials of V_i . w
+// (i <= j) when `dots`, or of w . w otherwise.
 template <typename T>
 __global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__restrict__ W, long long S, int j,
-                                                  const Gs2 *gs, const double *part_in, double *part_out, int dots,
-                                                  double *hkeep)
+                                                  const Gs2 *gs, const double *__restrict__ hin, double *part_out,
+                                                  int dots)
 {
     __shared__ double red[SLM_RED_DOUBLES];
     __shared__ double hs[SLM_KMAX + 1];
     const int c = blockIdx.y;
     if (gs[c].done) return;
     const int nb = gridDim.x;
-    if (threadIdx.x <= j) {
-        const double hv = part_sum(part_in, c, nb, threadIdx.x);
-        hs[threadIdx.x] = hv;
-        if (hkeep && blockIdx.x == 0) hkeep[c * (SLM_KMAX + 1) + threadIdx.x] = hv;
-    }
+    if (threadIdx.x <= j) hs[threadIdx.x] = hin[(long long)c * NPART + threadIdx.x];
     __syncthreads();
     const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
     double h[SLM_KMAX + 1];
@@ -266,19 +277,19 @@ __global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__r
     if (threadIdx.x < nv) part_out[((long long)c * nb + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
-// Givens recurrence, one thread per system.  h = hkeep (pass 1) + pass-2
-// coefficients, hn from the norm partials (Sec. 3.3 GMRES, same arithmetic
+// Givens recurrence, one thread per system: h = pass-1 + pass-2
+// coefficients, hn from the reduced norm (Sec. 3.3 GMRES, same arithmetic
 // order as the 1D kernel).
-__global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *hkeep, const double *part2,
-                          const double *partn, int nb, double rtol, int kmax)
+__global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *h1, const double *h2, const double *nn,
+                          double rtol, int kmax)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nsys) return;
     Gs2 &g = gs[c];
     if (g.done) return;
     double hc[SLM_KMAX + 1];
-    for (int i = 0; i <= j; ++i) hc[i] = hkeep[c * (SLM_KMAX + 1) + i] + part_sum(part2, c, nb, i);
-    const double hn = sqrt(part_sum(partn, c, nb, 0));
+    for (int i = 0; i <= j; ++i) hc[i] = h1[(long long)c * NPART + i] + h2[(long long)c * NPART + i];
+    const double hn = sqrt(nn[(long long)c * NPART]);
     for (int i = 0; i < j; ++i) {
         const double t0 = g.cs[i] * hc[i] + g.sn[i] * hc[i + 1];
         const double t1 = -g.sn[i] * hc[i] + g.cs[i] * hc[i + 1];
@@ -452,17 +463,22 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             Gs2 *gs = (Gs2 *)ws_at(P, P.g2s);
             double *pa = (double *)ws_at(P, P.g2p), *pb = pa + (long long)P.capg * nb * NPART;
             double *pc = pb + (long long)P.capg * nb * NPART;
-            double *hk = pc + (long long)P.capg * nb * NPART;
+            double *r1 = pc + (long long)P.capg * nb * NPART, *r2 = r1 + (long long)P.capg * NPART;
+            double *r3 = r2 + (long long)P.capg * NPART;
             const double *sig = (const double *)ws_at(P, L.sigma);
             hipLaunchKernelGGL(g2_norm0<T>, grid, dim3(TPB), 0, st, rhs, S, pa);
-            hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, rhs, S, pa, nb, V, gs, a.kmax);
+            hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, 1, (const Gs2 *)nullptr, r3);
+            hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, rhs, S, r3, V, gs, a.kmax);
             for (int j = 0; j < a.kmax; ++j) {
                 if ((e = launch_matvec<T>(P.d.p, grid, st, V, W, S, nx, sig, plane, n_first0 + k, a.stride_chain, j, gs,
                                           pa, P.d.dim, a.adj, a.adj, L.N)) != hipSuccess)
                     return e;
-                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, pa, pb, 1, hk);
-                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, pb, pc, 0, (double *)nullptr);
-                hipLaunchKernelGGL(g2_givens, dim3((nch + 63) / 64), dim3(64), 0, st, gs, nch, j, hk, pb, pc, nb,
+                hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, j + 1, gs, r1);
+                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, r1, pb, 1);
+                hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pb, nb, j + 1, gs, r2);
+                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, r2, pc, 0);
+                hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pc, nb, 1, gs, r3);
+                hipLaunchKernelGGL(g2_givens, dim3((nch + 63) / 64), dim3(64), 0, st, gs, nch, j, r1, r2, r3,
                                    a.rtol, a.kmax);
                 hipLaunchKernelGGL(g2_normalize<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs);
             }

@@ -9,6 +9,20 @@ namespace slmk {
 
 constexpr int COARSE_MAXB = 512;
 
+// Workgroup size of the level-0 chain kernel for an nx-point slice and a
+// sweep of `nchains` chains.  Up to 2047 points, or when the sweep has too
+// few chains to give every CU two of them: one node per thread (at most 1024
+// threads), the shortest step latency.  Otherwise, from 2048 points: eight
+// nodes per thread, so a 4096-point chain runs in 512 threads and two chains
+// share a CU (LDS and registers allow it), overlapping one chain's barriers
+// and start-up with the other's steps.
+__host__ __device__ inline int fine_block(int nx, long long nchains)
+{
+    if (nx >= 2048 && nchains >= 512)
+        return ((nx / 8 + 63) / 64) * 64 < SLM_MAXB ? ((nx / 8 + 63) / 64) * 64 : SLM_MAXB;
+    return nx >= SLM_MAXB ? SLM_MAXB : ((nx + 63) / 64) * 64;
+}
+
 // Interpolate the LDS slice `s` at the departure point of node i whose
 // displacement is d cells (xi = x_i - d h): x_E = x_{i - floor(d)},
 // eps = d - floor(d) (eq. depart_decompose).

@@ -392,7 +392,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
             P->g2v = take(capg * (SLM_KMAX + 1) * S * el);
             P->g2w = take(capg * S * el);
             P->g2s = take(capg * sizeof(Gs2));
-            P->g2p = take((3 * capg * (size_t)P->nb2 * SLM_NPART2 + capg * (SLM_KMAX + 1)) * sizeof(double));
+            P->g2p = take((3 * capg * (size_t)P->nb2 * SLM_NPART2 + 3 * capg * SLM_NPART2) * sizeof(double));
         }
     }
     if (d->adjoint) {
@@ -444,6 +444,7 @@ int slm_plan_setup(slm_plan *P, void *d_ws, size_t bytes, void *stream)
     hipStream_t st = (hipStream_t)stream;
     P->ws = (char *)d_ws;
     P->ready = false;
+    P->adj_ready = false;                   // the inverse stencil index follows the departure points
     HIPCHK(P->d.dim == 1 ? launch_trace_1d(*P, st) : launch_trace_2d(*P, st));
     for (int l = 1; l < P->L; ++l) HIPCHK(P->d.dim == 1 ? launch_backtrack_1d(*P, l, st) : launch_backtrack_2d(*P, l, st));
     P->ready = true;
