@@ -80,7 +80,8 @@ hipError_t coarse_launch(const ChainArgs &a, int nchains, hipStream_t st)
     size_t o1, o2, o3;
     const size_t lds = coarse_lds_parts<T, EPT>(a.nx, &o1, &o2, &o3);
     const int block = ((a.nx + EPT - 1) / EPT + 63) / 64 * 64;
-    return launch(coarse1d<T, P, EPT>, nchains, block, lds, a, st);
+    if (a.nx == EPT * block) return launch(coarse1d<T, P, EPT, true>, nchains, block, lds, a, st);
+    return launch(coarse1d<T, P, EPT, false>, nchains, block, lds, a, st);
 }
 
 // Elements per thread: the smallest power of two that keeps the workgroup at

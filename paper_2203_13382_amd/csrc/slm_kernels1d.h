@@ -195,7 +195,9 @@ struct GmresScalars {
     int flag;
 };
 
-template <typename T, int P, int EPT>
+// FULL: the slice fills the workgroup exactly (nx == EPT * blockDim), so no
+// node guard or ragged-tail wrap is needed.
+template <typename T, int P, int EPT, bool FULL = false>
 struct Gmres1D {
     T V[SLM_KMAX + 1][EPT];
     T w[EPT];
@@ -215,7 +217,7 @@ struct Gmres1D {
         const int i0 = tid * EPT;
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
-            if (i0 + e < nx) xp[pidx<EPT>(i0 + e)] = V[JJ][e];
+            if (FULL || i0 + e < nx) xp[pidx<EPT>(i0 + e)] = V[JJ][e];
         __syncthreads();
         if (JJ > 0 && gs->flag) return true;
         // w = V_JJ - sigma .* (D_{p+1} V_JJ) over the window i0-q .. i0+EPT-1+q
@@ -227,13 +229,13 @@ struct Gmres1D {
             il += il < 0 ? nx : 0;
             int ir = i0 + EPT + t;
             ir -= ir >= nx ? nx : 0;             // periodic (ragged tails wrap too)
-            win[t] = i0 < nx ? xp[pidx<EPT>(il)] : T(0);
-            win[EPT + q + t] = i0 < nx ? xp[pidx<EPT>(ir)] : T(0);
+            win[t] = (FULL || i0 < nx) ? xp[pidx<EPT>(il)] : T(0);
+            win[EPT + q + t] = (FULL || i0 < nx) ? xp[pidx<EPT>(ir)] : T(0);
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) win[q + e] = V[JJ][e];
         // ragged tail: neighbours past nx wrap to the start of the slice
-        if (i0 + EPT > nx) {
+        if (!FULL && i0 + EPT > nx) {
 #pragma unroll
             for (int e = 0; e < EPT + q; ++e) {
                 const int i = i0 + e;
@@ -242,7 +244,7 @@ struct Gmres1D {
         }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
-            if (i0 + e < nx) {
+            if (FULL || i0 + e < nx) {
                 double dv = 0.0;
 #pragma unroll
                 for (int t = 0; t <= 2 * q; ++t) dv += DTaps<P>::t[t] * double(win[e + t]);
@@ -407,7 +409,7 @@ __host__ __device__ inline size_t coarse_lds_parts(int nx, size_t *o_sg, size_t 
     return o + sizeof(GmresScalars);
 }
 
-template <typename T, int P, int EPT>
+template <typename T, int P, int EPT, bool FULL = false>
 __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned char *smem)
 {
     const int tid = threadIdx.x, nx = a.nx;
@@ -432,7 +434,7 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
     for (int e = 0; e < EPT; ++e) {
         const int i = i0 + e;
         T s = T(0);
-        if (i < nx) {
+        if (FULL || i < nx) {
             if (Cin) s = Cin[(long long)j * a.cin_stride + i];
             sl[i] = s;
             if (Vout && a.write_start) Vout[n_first * S + i] = s;
@@ -442,15 +444,15 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
     }
     __syncthreads();
     int rb = 0;
-    Gmres1D<T, P, EPT> gm;
+    Gmres1D<T, P, EPT, FULL> gm;
     unsigned long long nsolve = 0, niter = 0;
     for (int k = 0; k < a.nsteps; ++k) {
         const long long n = n_first + k;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = i0 + e;
-            if (i < nx) sgp[pidx<EPT>(i)] = a.sigma[n * S + i];
-            val[e] = i < nx ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
+            if (FULL || i < nx) sgp[pidx<EPT>(i)] = a.sigma[n * S + i];
+            val[e] = (FULL || i < nx) ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
         }
         __syncthreads();                         // every read of the slice is done, sigma staged
         niter += gm.solve(val, sgp, xp, red, rb, gs, a.kmax, a.rtol, nx);
@@ -459,7 +461,7 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = i0 + e;
-            if (i < nx) {
+            if (FULL || i < nx) {
                 if (G) val[e] += G[(n + 1) * S + i];
                 sl[i] = val[e];
                 if (wv) Vout[(n + 1) * S + i] = val[e];
@@ -470,7 +472,7 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
     if (Cout) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
-            if (i0 + e < nx) Cout[(long long)(j + a.cout_shift) * S + i0 + e] = val[e];
+            if (FULL || i0 + e < nx) Cout[(long long)(j + a.cout_shift) * S + i0 + e] = val[e];
     }
     if (a.R) {
         const T *Cref = static_cast<const T *>(a.Cref);
@@ -479,7 +481,7 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = i0 + e;
-            if (i < nx) {
+            if (FULL || i < nx) {
                 const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
                 R[(long long)(j + 1) * S + i] = r;
                 acc[0] += double(r) * double(r);
@@ -494,11 +496,11 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
     }
 }
 
-template <typename T, int P, int EPT>
+template <typename T, int P, int EPT, bool FULL>
 __global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    coarse_chain<T, P, EPT>(a, blockIdx.x, smem);
+    coarse_chain<T, P, EPT, FULL>(a, blockIdx.x, smem);
 }
 
 // Prefetch depth of the displacement ring: about 64 bytes per lane in
