@@ -142,16 +142,29 @@ __device__ __forceinline__ double dpp_f64(double x)
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Sum over the 64 lanes of a wavefront; every lane receives the total.  The
-// four in-row steps use DPP, the two cross-row steps ds_bpermute.
-__device__ __forceinline__ double wave_sum(double x)
+// DPP broadcast of a double: lanes in the rows of ROWMASK receive the value
+// of the lane CTRL selects (row_bcast:15 / row_bcast:31), the others 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_bcast_f64(double x)
+{
+    const unsigned long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffull), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wavefront, all in DPP (no LDS traffic): four
+// in-row steps leave every lane with its 16-lane row's sum, then
+// row_bcast:15 and row_bcast:31 carry the row sums up.  The total is exact
+// in lane 63 only (the other lanes hold partial sums).
+__device__ __forceinline__ double wave_sum_last(double x)
 {
     x += dpp_f64<0xB1>(x);    // lanes i ^ 1
     x += dpp_f64<0x4E>(x);    // lanes i ^ 2
     x += dpp_f64<0x141>(x);   // the other quad of the 8-lane half row
     x += dpp_f64<0x140>(x);   // the other half of the 16-lane row
-    x += __shfl_xor(x, 16, SLM_WAVE);
-    x += __shfl_xor(x, 32, SLM_WAVE);
+    x += dpp_bcast_f64<0x142, 0xA>(x);   // rows 1, 3 += last lane of rows 0, 2
+    x += dpp_bcast_f64<0x143, 0xC>(x);   // rows 2, 3 += lane 31
     return x;
 }
 
@@ -167,8 +180,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red, int buf)
     const int nw = blockDim.x / SLM_WAVE;
     double *r = red + buf * (SLM_MAXB / SLM_WAVE) * 16;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    if (lane == 0) {
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum_last(v[i]);
+    if (lane == SLM_WAVE - 1) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) r[wid * 16 + i] = v[i];
     }
@@ -202,8 +215,8 @@ __device__ __forceinline__ void block_sum_u(double (&v)[NV], double *red, int bu
     const int nw = blockDim.x / SLM_WAVE;
     double *r = red + buf * (SLM_MAXB / SLM_WAVE) * 16;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    if (lane == 0) {
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum_last(v[i]);
+    if (lane == SLM_WAVE - 1) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) r[wid * 16 + i] = v[i];
     }
