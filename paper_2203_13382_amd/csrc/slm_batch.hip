@@ -253,9 +253,9 @@ struct Builder {
 
     // Level-0 items are grouped by (p, workgroup size, elements per thread)
     // of their slice, the shape the per-level kernel would use.
-    static void fine_shape(int nx, int &block, int &ept)
+    static void fine_shape(int nx, long long nitems, int &block, int &ept)
     {
-        block = fine_block(nx, 1 << 30);   // a batch sweep has many items
+        block = fine_block(nx, nitems);
         const int e = (nx + block - 1) / block;
         ept = e <= 1 ? 1 : e <= 2 ? 2 : e <= 4 ? 4 : 8;
     }
@@ -264,7 +264,7 @@ struct Builder {
         std::vector<std::array<int, 3>> keys;
         for (const auto &it : v) {
             int b, e;
-            fine_shape(it.a.nx, b, e);
+            fine_shape(it.a.nx, (long long)v.size(), b, e);
             const std::array<int, 3> k{it.a.p, b, e};
             if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
         }
@@ -274,7 +274,7 @@ struct Builder {
             int nxg = 0;
             for (const auto &it : v) {
                 int b, e;
-                fine_shape(it.a.nx, b, e);
+                fine_shape(it.a.nx, (long long)v.size(), b, e);
                 if (it.a.p == k[0] && b == k[1] && e == k[2]) {
                     g.push_back(it);
                     nxg = std::max(nxg, it.a.nx);
