@@ -33,10 +33,10 @@ int nblk(long long S)
 // departure point, E = k - floor(d) per axis.
 __device__ __forceinline__ int cell_of(long long k, int nx, int dim, double dx, double dy)
 {
-    const int ix = (int)(k % nx);
+    int ix, iy;
+    split_xy(k, nx, ix, iy);
     const int ex = wrap_mod(ix - (int)floor(dx), nx);
     if (dim == 1) return ex;
-    const int iy = (int)(k / nx);
     const int ey = wrap_mod(iy - (int)floor(dy), nx);
     return ey * nx + ex;
 }
@@ -161,7 +161,9 @@ __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ s
     const double *dxs = disp + nd * S, *dys = disp + plane + nd * S;
     const int *en = end + nd * S, *pm = perm + nd * S;
     for (long long t = (long long)blockIdx.x * TPB + threadIdx.x; t < S; t += (long long)gridDim.x * TPB) {
-        const int tx = (int)(t % nx), ty = dim == 2 ? (int)(t / nx) : 0;
+        int tx, ty;
+        split_xy(t, nx, tx, ty);
+        if (dim != 2) ty = 0;
         double acc = 0.0;
         const int nby = dim == 2 ? P : 0;
         for (int b = 0; b <= nby; ++b) {
@@ -205,7 +207,9 @@ __global__ void __launch_bounds__(TPB) stepF_kernel(const double *__restrict__ s
     const long long n = n_first + (long long)c * stride;
     const double *u = src + c * src_stride;
     for (long long t = (long long)blockIdx.x * TPB + threadIdx.x; t < S; t += (long long)gridDim.x * TPB) {
-        const int tx = (int)(t % nx), ty = dim == 2 ? (int)(t / nx) : 0;
+        int tx, ty;
+        split_xy(t, nx, tx, ty);
+        if (dim != 2) ty = 0;
         const double dx = disp[n * S + t];
         const double fx = floor(dx);
         double wx[P + 1];
@@ -361,7 +365,9 @@ __global__ void __launch_bounds__(TPB) grad_kernel(const double *__restrict__ U,
     for (long long t = (long long)blockIdx.x * TPB + threadIdx.x; t < S; t += (long long)gridDim.x * TPB) {
         const double l = lm[t];
         if (l == 0.0) continue;
-        const int tx = (int)(t % nx), ty = DIM == 2 ? (int)(t / nx) : 0;
+        int tx, ty;
+        split_xy(t, nx, tx, ty);
+        if (DIM != 2) ty = 0;
         const double dx = disp[n * S + t], fx = floor(dx);
         double wx[P + 1], dwx[P + 1];
         weights_eps<P>(dx - fx, wx, dwx);

@@ -174,6 +174,7 @@ size_t coarse_lds(int nx, int ept)
 struct slm_batch {
     struct Op {
         int kind;             // 0 fine, 1 coarse, 2 control, 3 checked copy, 4 unchecked copy
+        int group;            // ops of one sweep split by launch shape run concurrently (0: alone)
         int p, ept;           // coarse class
         size_t off;           // device offset of the op's items / copy descriptors
         int n;                // items / descriptors
@@ -195,6 +196,8 @@ struct slm_batch {
     int grid_mult = 2, order_desc = 1, cus = 256;   // launch shape (autotuned)
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
+    std::vector<hipStream_t> side;      // streams for the concurrent ops of a group
+    std::vector<hipEvent_t> ev;         // fork event + one join event per side stream
     // host staging that must outlive asynchronous copies until the next sync
     std::vector<unsigned char> blob, blob2;
     std::vector<BCtl> hctl, hon;
@@ -246,8 +249,9 @@ struct Builder {
     const slm_batch &B;
     std::vector<BItem> items;
     std::vector<BCopy> copies;
-    struct Pending { int kind, p, ept, first, n, block; size_t lds; long long maxe; };
+    struct Pending { int kind, p, ept, first, n, block; size_t lds; long long maxe; int group = 0; };
     std::vector<Pending> pend;
+    int next_group = 1;
 
     explicit Builder(const slm_batch &b) : B(b) {}
 
@@ -284,9 +288,10 @@ struct Builder {
                 std::stable_sort(g.begin(), g.end(), [](const BItem &x, const BItem &y) {
                     return (long long)x.a.nx * x.a.nsteps > (long long)y.a.nx * y.a.nsteps;
                 });
-            pend.push_back(Pending{0, k[0], k[2], (int)items.size(), (int)g.size(), k[1], 0, nxg});
+            pend.push_back(Pending{0, k[0], k[2], (int)items.size(), (int)g.size(), k[1], 0, nxg, next_group});
             items.insert(items.end(), g.begin(), g.end());
         }
+        ++next_group;
     }
     void coarse(const std::vector<BItem> &v)
     {
@@ -302,9 +307,10 @@ struct Builder {
                     lds = std::max(lds, B.fp32 ? coarse_lds<float>(it.a.nx, e) : coarse_lds<double>(it.a.nx, e));
                 }
                 if (g.empty()) continue;
-                pend.push_back(Pending{1, p, e, (int)items.size(), (int)g.size(), block, lds, 0});
+                pend.push_back(Pending{1, p, e, (int)items.size(), (int)g.size(), block, lds, 0, next_group});
                 items.insert(items.end(), g.begin(), g.end());
             }
+        ++next_group;
     }
     void control() { pend.push_back(Pending{2, 0, 0, 0, 0, 0, 0, 0}); }
     void copy(const std::vector<BCopy> &v, bool checked)
@@ -326,6 +332,7 @@ struct Builder {
         for (const auto &pd : pend) {
             slm_batch::Op o{};
             o.kind = pd.kind;
+            o.group = pd.group;
             o.p = pd.p;
             o.ept = pd.ept;
             o.n = pd.n;
@@ -404,29 +411,89 @@ hipError_t coarse_launch(const slm_batch &B, const slm_batch::Op &o, hipStream_t
 #undef CB
 }
 
-// Enqueue a program of ops on `st` (also used under stream capture).
-int run_ops(slm_batch *B, const std::vector<slm_batch::Op> &ops, hipStream_t st)
+// One op on `st`; persistent sweeps pull items through counter slot `slot`.
+int run_op(slm_batch *B, const slm_batch::Op &o, hipStream_t st, int slot)
 {
-    unsigned *cnt = (unsigned *)(B->ws + B->o_counter);
+    unsigned *cnt = (unsigned *)(B->ws + B->o_counter) + slot;
     int *rem = (int *)(B->ws + B->o_remaining);
     BCtl *ctl = (BCtl *)(B->ws + B->o_ctl);
-    for (const auto &o : ops) {
-        if (o.kind == 0 || o.kind == 1) {
-            hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, st, cnt);
-            BCHK(hipGetLastError());
-            if (o.kind == 0) BCHK(B->fp32 ? fine_launch<float>(*B, o, st, cnt) : fine_launch<double>(*B, o, st, cnt));
-            else BCHK(B->fp32 ? coarse_launch<float>(*B, o, st, cnt) : coarse_launch<double>(*B, o, st, cnt));
-        } else if (o.kind == 2) {
-            hipLaunchKernelGGL(batch_control, dim3(B->n), dim3(CTL_THREADS), 0, st, ctl, B->hist_cap, rem);
-            BCHK(hipGetLastError());
-        } else {
-            const long long g = std::max(1LL, std::min(4096LL, (o.maxelems + 255) / 256));
-            const BCopy *c = (const BCopy *)(B->ws + o.off);
-            const int chk = o.kind == 3 ? 1 : 0;
-            if (B->fp32) hipLaunchKernelGGL(batch_copy<float>, dim3((unsigned)g, o.n), dim3(256), 0, st, c, ctl, chk);
-            else hipLaunchKernelGGL(batch_copy<double>, dim3((unsigned)g, o.n), dim3(256), 0, st, c, ctl, chk);
-            BCHK(hipGetLastError());
+    if (o.kind == 0 || o.kind == 1) {
+        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, st, cnt);
+        BCHK(hipGetLastError());
+        if (o.kind == 0) BCHK(B->fp32 ? fine_launch<float>(*B, o, st, cnt) : fine_launch<double>(*B, o, st, cnt));
+        else BCHK(B->fp32 ? coarse_launch<float>(*B, o, st, cnt) : coarse_launch<double>(*B, o, st, cnt));
+    } else if (o.kind == 2) {
+        hipLaunchKernelGGL(batch_control, dim3(B->n), dim3(CTL_THREADS), 0, st, ctl, B->hist_cap, rem);
+        BCHK(hipGetLastError());
+    } else {
+        const long long g = std::max(1LL, std::min(4096LL, (o.maxelems + 255) / 256));
+        const BCopy *c = (const BCopy *)(B->ws + o.off);
+        const int chk = o.kind == 3 ? 1 : 0;
+        if (B->fp32) hipLaunchKernelGGL(batch_copy<float>, dim3((unsigned)g, o.n), dim3(256), 0, st, c, ctl, chk);
+        else hipLaunchKernelGGL(batch_copy<double>, dim3((unsigned)g, o.n), dim3(256), 0, st, c, ctl, chk);
+        BCHK(hipGetLastError());
+    }
+    return SLM_OK;
+}
+
+// Side streams and events for the largest group of `ops` (created outside
+// any stream capture).
+int ensure_side(slm_batch *B, const std::vector<slm_batch::Op> &ops)
+{
+    int most = 1;
+    for (size_t i = 0; i < ops.size();) {
+        size_t j = i + 1;
+        if (ops[i].group)
+            while (j < ops.size() && ops[j].group == ops[i].group) ++j;
+        most = std::max(most, (int)(j - i));
+        i = j;
+    }
+    while ((int)B->side.size() < most - 1) {
+        hipStream_t s2 = nullptr;
+        BCHK(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+        B->side.push_back(s2);
+    }
+    while ((int)B->ev.size() < most) {
+        hipEvent_t e = nullptr;
+        BCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        B->ev.push_back(e);
+    }
+    return SLM_OK;
+}
+
+// Enqueue a program of ops on `st` (also used under stream capture).  The
+// ops of one group (a sweep split by launch shape) are independent: they
+// fork onto side streams and join back, so a long chain of one shape does
+// not wait behind another shape's tail.
+int run_ops(slm_batch *B, const std::vector<slm_batch::Op> &ops, hipStream_t st)
+{
+    for (size_t i = 0; i < ops.size();) {
+        size_t j = i + 1;
+        if (ops[i].group)
+            while (j < ops.size() && ops[j].group == ops[i].group) ++j;
+        const int cnt = (int)(j - i);
+        if (cnt == 1) {
+            const int rc = run_op(B, ops[i], st, 0);
+            if (rc) return rc;
+            i = j;
+            continue;
         }
+        if (cnt > 63) return bfail(B, SLM_EUNSUPPORTED, "too many launch shapes in one batch sweep");
+        if ((int)B->side.size() < cnt - 1 || (int)B->ev.size() < cnt)
+            return bfail(B, SLM_EINVAL, "side streams not prepared for this program");
+        BCHK(hipEventRecord(B->ev[0], st));
+        for (int k = 1; k < cnt; ++k) {
+            BCHK(hipStreamWaitEvent(B->side[k - 1], B->ev[0], 0));
+            const int rc = run_op(B, ops[i + k], B->side[k - 1], k);
+            if (rc) return rc;
+        }
+        const int rc = run_op(B, ops[i], st, 0);
+        if (rc) return rc;
+        for (int k = 1; k < cnt; ++k) {
+            BCHK(hipEventRecord(B->ev[k], B->side[k - 1]));
+            BCHK(hipStreamWaitEvent(st, B->ev[k], 0));
+        }
+        i = j;
     }
     return SLM_OK;
 }
@@ -553,6 +620,7 @@ int upload_cycle(slm_batch *B, hipStream_t st)
     build_cycle(*B, bd);
     const size_t bytes = bd.finish(B->o_items, B->blob, B->cycle);
     if (bytes > B->items_cap) return bfail(B, SLM_EWORKSPACE, "batch work-list region too small");
+    if (const int rc = ensure_side(B, B->cycle)) return rc;
     if (bytes) BCHK(hipMemcpyAsync(B->ws + B->o_items, B->blob.data(), bytes, hipMemcpyHostToDevice, st));
     BCHK(hipStreamSynchronize(st));
     if (B->gexec) {
@@ -585,6 +653,7 @@ int run_once(slm_batch *B, const Builder &bd, hipStream_t st)
     std::vector<slm_batch::Op> ops;
     const size_t bytes = bd.finish(B->o_sitems, B->blob2, ops);
     if (bytes > B->sitems_cap) return bfail(B, SLM_EWORKSPACE, "batch solve work-list region too small");
+    if (const int rc = ensure_side(B, ops)) return rc;
     if (bytes) BCHK(hipMemcpyAsync(B->ws + B->o_sitems, B->blob2.data(), bytes, hipMemcpyHostToDevice, st));
     int rc = run_ops(B, ops, st);
     if (rc) return rc;
@@ -657,6 +726,8 @@ void slm_batch_destroy(slm_batch *B)
     if (!B) return;
     if (B->gexec) (void)hipGraphExecDestroy(B->gexec);
     if (B->cap_stream) (void)hipStreamDestroy(B->cap_stream);
+    for (auto s2 : B->side) (void)hipStreamDestroy(s2);
+    for (auto e : B->ev) (void)hipEventDestroy(e);
     for (auto *P : B->plans) slm_plan_destroy(P);
     delete B;
 }

@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(TPB) step2d_kernel(const T *__restrict__ src, 
     const T *s = src ? src + c * src_stride : nullptr;
     T *d = dst + c * dst_stride;
     for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
-        const int i = (int)(id % nx), j = (int)(id / nx);
+        int i, j;
+        split_xy(id, nx, i, j);
         T v = s ? interp2<P, T, TD>(s, i, j, disp[n * S + id], disp[plane + n * S + id], nx) : T(0);
         if (G) v += G[(n + 1) * S + id];
         d[id] = v;
@@ -213,7 +214,9 @@ __global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__r
 #pragma unroll
     for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
     for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
-        const int i = (int)(id % nx), jr = dim == 2 ? (int)(id / nx) : 0;
+        int i, jr;
+        split_xy(id, nx, i, jr);
+        if (dim != 2) jr = 0;
         double dxv = 0.0, dyv = 0.0;
 #pragma unroll
         for (int t = -q; t <= q; ++t) {

@@ -124,6 +124,17 @@ template <> struct DTaps<5> { static constexpr int q = 3; static constexpr doubl
 template <> struct DTaps<2> { static constexpr int q = 1; static constexpr double t[3] = {0, 0, 0}; };
 template <> struct DTaps<4> { static constexpr int q = 1; static constexpr double t[3] = {0, 0, 0}; };
 
+// Column i and row j of point id of an nx-wide slice, in 32-bit arithmetic
+// (a slice holds fewer than 2^31 points; 64-bit division is a long software
+// sequence on the GPU).
+__device__ __forceinline__ void split_xy(long long id, int nx, int &i, int &j)
+{
+    const unsigned u = (unsigned)id, n = (unsigned)nx;
+    const unsigned q = u / n;
+    j = (int)q;
+    i = (int)(u - q * n);
+}
+
 __device__ __forceinline__ int wrap_mod(int a, int n)
 {
     int r = a % n;

@@ -47,7 +47,8 @@ __global__ void trace_kernel(int nx, long long S, int nt, double dt, double h, W
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int n = blockIdx.y;
     if (id >= S) return;
-    const int i = (int)(id % nx), jy = (int)(id / nx);
+    int i, jy;
+    split_xy(id, nx, i, jy);
     double dx, dy;
     erk_back<R, DIM>(fa, fb, -1.0 + i * h, DIM == 2 ? -1.0 + jy * h : 0.0, (n + 1) * dt, dt, h, dx, dy);
     const long long o = (long long)n * S + id, plane = (long long)nt * S;
@@ -106,7 +107,8 @@ __global__ void backtrack2d_kernel(int nx, int m, int Nl, int p, const double *_
     const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int n = blockIdx.y;
     if (id >= S || n >= Nl) return;
-    const int i = (int)(id % nx), jy = (int)(id / nx);
+    int i, jy;
+    split_xy(id, nx, i, jy);
     const long long base = (long long)n * m;
     const double *px = dprev, *py = dprev + plane_prev;
     double Dx = px[(base + m - 1) * S + id], Dy = py[(base + m - 1) * S + id];
