@@ -22,6 +22,8 @@
 // coarse levels S_l^T [I - D_x diag(sx) - D_y diag(sy)]^{-1}: the GMRES
 // right-hand side is the incoming slice, the matvec the transposed one, and
 // the transposed interpolation follows the solve.
+#include <cmath>
+
 #include "slm_internal.h"
 
 namespace {
@@ -79,6 +81,73 @@ __global__ void __launch_bounds__(TPB) step2d_kernel(const T *__restrict__ src, 
         T v = s ? interp2<P, T, TD>(s, i, j, disp[n * S + id], disp[plane + n * S + id], nx) : T(0);
         if (G) v += G[(n + 1) * S + id];
         d[id] = v;
+        if (Vout) Vout[(n + 1) * S + id] = v;
+    }
+}
+
+// Level-0 step with the source window staged in LDS.  A workgroup computes a
+// TX x TY tile of outputs; every departure point of the tile lies within F
+// cells of its node (F bounds |floor(d)| from the wave speed), so the tile's
+// stencils read only the window [x0 - F - LO, x0 + TX - 1 + F + HI] x (same in
+// y), loaded once with coalesced reads.  The (p+1)^2-tap gathers then hit LDS
+// instead of the texture path.  A stencil outside the window (not expected)
+// falls back to global reads, so the result never depends on F.
+constexpr int TILE_X = 64, TILE_Y = 16;
+
+template <typename T, typename TD, int P>
+__global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ src, long long src_stride,
+                                                          T *__restrict__ dst, long long dst_stride,
+                                                          const TD *__restrict__ disp, long long plane, int nx,
+                                                          long long n_first, int stride, const T *__restrict__ G,
+                                                          T *__restrict__ Vout, int F)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *win = reinterpret_cast<T *>(smem_raw);
+    constexpr int LO = P / 2 + 1, HI = P / 2;      // node offsets around x_E, any p
+    const long long S = (long long)nx * nx;
+    const int c = blockIdx.y;
+    const long long n = n_first + (long long)c * stride;
+    const T *s = src + c * src_stride;
+    const int ntx = (nx + TILE_X - 1) / TILE_X;
+    const int x0 = (int)(blockIdx.x % ntx) * TILE_X, y0 = (int)(blockIdx.x / ntx) * TILE_Y;
+    const int wx = TILE_X + 2 * F + LO + HI, wy = TILE_Y + 2 * F + LO + HI;
+    const int ox = x0 - F - LO, oy = y0 - F - LO;   // window origin (unwrapped)
+    for (int k = threadIdx.x; k < wx * wy; k += TPB) {
+        const int r = k / wx, q = k - r * wx;
+        const int gy = wrap_mod(oy + r, nx), gx = wrap_mod(ox + q, nx);
+        win[k] = s[(long long)gy * nx + gx];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < TILE_X * TILE_Y; k += TPB) {
+        const int ly = k / TILE_X, lx = k - ly * TILE_X;
+        const int i = x0 + lx, j = y0 + ly;
+        if (i >= nx || j >= nx) continue;
+        const long long id = (long long)j * nx + i;
+        const TD dx = disp[n * S + id], dy = disp[plane + n * S + id];
+        const TD fx = floor(dx), fy = floor(dy);
+        const T ex = T(dx - fx), ey = T(dy - fy);
+        const int firstx = stencil_first<T>(P, ex), firsty = stencil_first<T>(P, ey);
+        const int bx = i - int(fx) + firstx - ox, by = j - int(fy) + firsty - oy;   // window coordinates
+        T v;
+        if (bx >= 0 && by >= 0 && bx + P < wx && by + P < wy) {
+            T wxv[P + 1], wyv[P + 1];
+            lagrange_weights<P, T>(-ex - T(firstx), wxv);
+            lagrange_weights<P, T>(-ey - T(firsty), wyv);
+            T acc = T(0);
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+                const T *row = win + (by + b) * wx + bx;
+                T ar = T(0);
+#pragma unroll
+                for (int a = 0; a <= P; ++a) ar += wxv[a] * row[a];
+                acc += wyv[b] * ar;
+            }
+            v = acc;
+        } else {
+            v = interp2<P, T, TD>(s, i, j, dx, dy, nx);
+        }
+        if (G) v += G[(n + 1) * S + id];
+        dst[c * dst_stride + id] = v;
         if (Vout) Vout[(n + 1) * S + id] = v;
     }
 }
@@ -390,6 +459,39 @@ hipError_t launch_step(int p, dim3 grid, hipStream_t st, const T *src, long long
     return hipGetLastError();
 }
 
+// Level-0 step, LDS-tiled when the window of a tile fits (F from the bound
+// on the displacement); the plain gather kernel otherwise.
+template <typename T, typename TD>
+hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src, long long ss, T *dst, long long ds,
+                        const TD *disp, long long plane, long long n_first, int stride, const T *G, T *Vout)
+{
+    const int nx = P.d.nx, p = P.d.p;
+    double a = 0.0, b = 0.0;
+    for (const auto &t : P.alpha) a += std::fabs(t.coef);
+    for (const auto &t : P.beta) b += std::fabs(t.coef);
+    const double dbound = P.d.dt / (2.0 / nx) * (a > b ? a : b);
+    const int F = (int)std::ceil(dbound) + 1;
+    const int wx = TILE_X + 2 * F + p / 2 + 1 + p / 2, wy = TILE_Y + 2 * F + p / 2 + 1 + p / 2;
+    const size_t lds = (size_t)wx * wy * sizeof(T);
+    if (F > 16 || lds > 48 * 1024) {
+        const dim3 grid(nblocks((long long)nx * nx), nch);
+        return launch_step<T, TD>(p, grid, st, src, ss, dst, ds, disp, plane, nx, n_first, stride, G, Vout);
+    }
+    const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
+    const dim3 grid(ntiles, nch);
+#define STEPT(PP) hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP>), grid, dim3(TPB), lds, st, src, ss, dst, ds, disp, \
+                                     plane, nx, n_first, stride, G, Vout, F)
+    switch (p) {
+    case 1: STEPT(1); break;
+    case 2: STEPT(2); break;
+    case 3: STEPT(3); break;
+    case 4: STEPT(4); break;
+    default: STEPT(5); break;
+    }
+#undef STEPT
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, const T *V, T *W, long long S, int nx, const double *sig,
                          long long plane, long long n_first, int stride, int j, const Gs2 *gs, double *part, int dim,
@@ -441,13 +543,12 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             if (e != hipSuccess) return e;
         } else if (level == 0) {
             if (P.d.precision == SLM_FP32_BULK)
-                e = launch_step<T, float>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S,
-                                          (const float *)ws_at(P, L.disp), plane, nx, n_first0 + k, a.stride_chain,
-                                          (const T *)a.G, vo);
+                e = launch_step0<T, float>(P, nch, st, bufs[cur], S, bufs[cur ^ 1], S, (const float *)ws_at(P, L.disp),
+                                           plane, n_first0 + k, a.stride_chain, (const T *)a.G, vo);
             else
-                e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S,
-                                           (const double *)ws_at(P, L.disp), plane, nx, n_first0 + k,
-                                           a.stride_chain, (const T *)a.G, vo);
+                e = launch_step0<T, double>(P, nch, st, bufs[cur], S, bufs[cur ^ 1], S,
+                                            (const double *)ws_at(P, L.disp), plane, n_first0 + k, a.stride_chain,
+                                            (const T *)a.G, vo);
             if (e != hipSuccess) return e;
         } else {
             // forward: interpolation into the GMRES right-hand side; adjoint:
