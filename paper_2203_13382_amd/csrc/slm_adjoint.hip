@@ -118,6 +118,23 @@ __global__ void __launch_bounds__(TPB) idx_sort(const int *__restrict__ end, int
     }
 }
 
+// Fractional parts of the sources' displacements in index order, so the
+// gather reads them contiguously.
+__global__ void __launch_bounds__(TPB) idx_eps(const double *__restrict__ disp, long long plane, long long S,
+                                               int dim, const int *__restrict__ perm, double *eps, long long eplane)
+{
+    const long long n = blockIdx.y;
+    for (long long q = (long long)blockIdx.x * TPB + threadIdx.x; q < S; q += (long long)gridDim.x * TPB) {
+        const int k = perm[n * S + q];
+        const double dx = disp[n * S + k];
+        eps[n * S + q] = dx - floor(dx);
+        if (dim == 2) {
+            const double dy = disp[plane + n * S + k];
+            eps[eplane + n * S + q] = dy - floor(dy);
+        }
+    }
+}
+
 // Lagrange weights and their derivatives with respect to eps at the
 // departure point (odd p: stencil nodes E-l .. E+r, fixed in eps).
 template <int P>
@@ -143,11 +160,32 @@ __device__ __forceinline__ void weights_eps(double eps, double (&w)[P + 1], doub
     }
 }
 
+// One Lagrange weight of the stencil: node j (0..P) at the shifted point z,
+// prod_{k != j} (z - k) / prod_{k != j} (j - k).
+template <int P>
+__device__ __forceinline__ double lweight(double z, int j)
+{
+    double pr = 1.0;
+#pragma unroll
+    for (int k = 0; k <= P; ++k)
+        if (k != j) pr *= z - (double)k;
+    // 1 / prod_{k != j} (j - k) = (-1)^{P-j} / (j! (P-j)!)
+    constexpr double f[6] = {1.0, 1.0, 2.0, 6.0, 24.0, 120.0};
+    double inv = 1.0;
+#pragma unroll
+    for (int t = 0; t <= P; ++t)
+        if (t == j) inv = ((P - t) & 1 ? -1.0 : 1.0) / (f[t] * f[P - t]);
+    return pr * inv;
+}
+
 // dst[c] = S^T(step) src[c] (+ G[n+1]); step = n, or Nl-1-n when rev.
+// Target t visits the p+1 cells per axis whose stencils cover it; the cell
+// fixes t's node index in each source's stencil, so a source costs its
+// loads and two single Lagrange weights (no index arithmetic per source).
 template <int P>
 __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ src, long long src_stride,
                                                     double *__restrict__ dst, long long dst_stride,
-                                                    const double *__restrict__ disp, long long plane,
+                                                    const double *__restrict__ eps, long long eplane,
                                                     const int *__restrict__ end, const int *__restrict__ perm,
                                                     int nx, int dim, long long S, long long n_first, int stride,
                                                     int rev, int Nl, const double *__restrict__ G,
@@ -158,7 +196,7 @@ __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ s
     const long long n = n_first + (long long)c * stride;
     const long long nd = rev ? Nl - 1 - n : n;
     const double *lam = src + c * src_stride;
-    const double *dxs = disp + nd * S, *dys = disp + plane + nd * S;
+    const double *exs = eps + nd * S, *eys = eps + eplane + nd * S;
     const int *en = end + nd * S, *pm = perm + nd * S;
     for (long long t = (long long)blockIdx.x * TPB + threadIdx.x; t < S; t += (long long)gridDim.x * TPB) {
         int tx, ty;
@@ -167,24 +205,22 @@ __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ s
         double acc = 0.0;
         const int nby = dim == 2 ? P : 0;
         for (int b = 0; b <= nby; ++b) {
-            const int ey = dim == 2 ? wrap_mod(ty + ell - b, nx) : 0;
+            int ey = 0;
+            if (dim == 2) {
+                ey = ty + ell - b;
+                ey += ey < 0 ? nx : 0;
+                ey -= ey >= nx ? nx : 0;
+            }
             for (int a = 0; a <= P; ++a) {
-                const int ex = wrap_mod(tx + ell - a, nx);
+                int ex = tx + ell - a;
+                ex += ex < 0 ? nx : 0;
+                ex -= ex >= nx ? nx : 0;
                 const long long cell = (long long)ey * nx + ex;
                 const int lo = cell ? en[cell - 1] : 0, hi = en[cell];
                 for (int q = lo; q < hi; ++q) {
-                    const int k = pm[q];
-                    double w[P + 1];
-                    const double dx = dxs[k];
-                    lagrange_weights<P, double>(-(dx - floor(dx)) + (double)ell, w);
-                    double wv = w[a];
-                    if (dim == 2) {
-                        double wy[P + 1];
-                        const double dy = dys[k];
-                        lagrange_weights<P, double>(-(dy - floor(dy)) + (double)ell, wy);
-                        wv *= wy[b];
-                    }
-                    acc += wv * lam[k];
+                    double wv = lweight<P>(-exs[q] + (double)ell, a);
+                    if (dim == 2) wv *= lweight<P>(-eys[q] + (double)ell, b);
+                    acc += wv * lam[pm[q]];
                 }
             }
         }
@@ -419,14 +455,21 @@ __global__ void __launch_bounds__(TPB) grad_kernel(const double *__restrict__ U,
     if (threadIdx.x < nq) gacc[((long long)(c0 + c) * gridDim.x + blockIdx.x) * NQ + threadIdx.x] += g[threadIdx.x];
 }
 
-// Fixed-order sum of the gradient slots of every (chain, block).
-__global__ void grad_reduce(const double *__restrict__ gacc, long long nslots, int nq, double *out)
+// Fixed-order sum of the gradient slots of every (chain, block): one
+// workgroup, each thread a strided subset, then the workgroup tree.
+__global__ void __launch_bounds__(TPB) grad_reduce(const double *__restrict__ gacc, long long nslots, int nq,
+                                                  double *out)
 {
-    const int q = threadIdx.x;
-    if (q >= nq) return;
-    double s = 0.0;
-    for (long long i = 0; i < nslots; ++i) s += gacc[i * NQ + q];
-    out[q] = s;
+    __shared__ double red[SLM_RED_DOUBLES];
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    for (long long i = threadIdx.x; i < nslots; i += TPB)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < nq) v[q] += gacc[i * NQ + q];
+    block_sum<NQ>(v, red, 0);
+    if (threadIdx.x < nq) out[threadIdx.x] = v[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(TPB) fill0(double *p, long long n)
@@ -454,6 +497,8 @@ hipError_t launch_adj_index(const slm_plan &P, int level, hipStream_t st)
         hipLaunchKernelGGL(idx_scan, dim3(nn), dim3(1024), 0, st, e, S);
         hipLaunchKernelGGL(idx_fill, dim3(nb, nn), dim3(TPB), 0, st, d, plane, S, P.d.nx, P.d.dim, e, pm);
         hipLaunchKernelGGL(idx_sort, dim3(nb, nn), dim3(TPB), 0, st, e, pm, S);
+        hipLaunchKernelGGL(idx_eps, dim3(nb, nn), dim3(TPB), 0, st, d, plane, S, P.d.dim, pm,
+                           (double *)ws_at(P, L.idx_eps) + n0 * S, N * S);
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -468,8 +513,10 @@ hipError_t launch_stepT(const slm_plan &P, int level, int nch, const double *src
     const long long S = P.S;
     const double *disp = (const double *)ws_at(P, L.disp);
     const int *end = (const int *)ws_at(P, L.idx_end), *perm = (const int *)ws_at(P, L.idx_perm);
+    const double *eps = (const double *)ws_at(P, L.idx_eps);
+    (void)disp;
     const dim3 grid(nblk(S), nch);
-#define ST(PP) hipLaunchKernelGGL((stepT_kernel<PP>), grid, dim3(TPB), 0, st, src, src_stride, dst, dst_stride, disp, \
+#define ST(PP) hipLaunchKernelGGL((stepT_kernel<PP>), grid, dim3(TPB), 0, st, src, src_stride, dst, dst_stride, eps, \
                                   (long long)L.N * S, end, perm, P.d.nx, P.d.dim, S, n_first, stride, rev, L.N, G, Vout)
     switch (P.d.p) {
     case 1: ST(1); break;
@@ -523,7 +570,7 @@ hipError_t launch_grad(const slm_plan &P, int nch, const double *U, long long u_
 
 hipError_t launch_grad_reduce(const slm_plan &P, int nchains, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(grad_reduce, dim3(1), dim3(64), 0, st, (const double *)ws_at(P, P.gacc),
+    hipLaunchKernelGGL(grad_reduce, dim3(1), dim3(TPB), 0, st, (const double *)ws_at(P, P.gacc),
                        (long long)nchains * nblk(P.S), P.nq, out);
     return hipGetLastError();
 }

@@ -473,11 +473,11 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
     const int F = (int)std::ceil(dbound) + 1;
     const int wx = TILE_X + 2 * F + p / 2 + 1 + p / 2, wy = TILE_Y + 2 * F + p / 2 + 1 + p / 2;
     const size_t lds = (size_t)wx * wy * sizeof(T);
-    if (F > 16 || lds > 48 * 1024) {
+    const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
+    if (F > 16 || lds > 48 * 1024 || (long long)ntiles * nch < 256) {   // too few tiles to fill the GPU
         const dim3 grid(nblocks((long long)nx * nx), nch);
         return launch_step<T, TD>(p, grid, st, src, ss, dst, ds, disp, plane, nx, n_first, stride, G, Vout);
     }
-    const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
     const dim3 grid(ntiles, nch);
 #define STEPT(PP) hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP>), grid, dim3(TPB), lds, st, src, ss, dst, ds, disp, \
                                      plane, nx, n_first, stride, G, Vout, F)

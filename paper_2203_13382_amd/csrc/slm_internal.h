@@ -19,6 +19,7 @@ struct LevelInfo {
     size_t C = 0;           // [(N/m+1)][S] T: C-point buffer (not on the coarsest level)
     size_t idx_end = 0;     // adjoint: [N][S] int, end of each stencil cell's source list
     size_t idx_perm = 0;    // adjoint: [N][S] int, sources ordered by stencil cell
+    size_t idx_eps = 0;     // adjoint: [dim][N][S] double, eps (and nu) of the sources in that order
 };
 
 // Per-system Givens state of the batched 2D GMRES.

@@ -400,6 +400,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
         for (int l = 0; l < P->L; ++l) {
             P->lv[l].idx_end = take((size_t)P->lv[l].N * S * sizeof(int));
             P->lv[l].idx_perm = take((size_t)P->lv[l].N * S * sizeof(int));
+            P->lv[l].idx_eps = take(dim * (size_t)P->lv[l].N * S * sizeof(double));
         }
         P->gcap = (int)(nc0 < 64 ? nc0 : 64);
         P->lamC = take((nc0 + 1) * S * sizeof(double));
