@@ -49,6 +49,11 @@ typedef struct { double coef, kx, px, ky, py, kt, pt; } slm_wave_term;
 enum { SLM_RELAX_F = 0, SLM_RELAX_FCF = 1 };            /* Sec. 2.2 */
 enum { SLM_TOL_ABS = 0, SLM_TOL_REL = 1 };
 enum { SLM_FP64 = 0, SLM_FP32_BULK = 1 };
+/* Coarse-grid operator: the modified SL operator of eq. (Phi_multilevel) /
+ * (BEOper_2D), or the rediscretized SL operator of Sec. 2.3 (a plain SL
+ * step of size m^l dt whose departure points are traced through the m^l
+ * fine-size ERK steps it spans, as in Sec. 4.3's comparison). */
+enum { SLM_COARSE_MODIFIED = 0, SLM_COARSE_REDISC = 2 };
 
 enum {
     SLM_OK = 0,                /* success / converged */
@@ -85,6 +90,8 @@ typedef struct {
     int precision;             /* SLM_FP64 or SLM_FP32_BULK */
     int adjoint;               /* 1: also size the workspace for slm_adjoint (needs SLM_FP64,
                                   odd p and at least two levels); 0: forward only */
+    int coarse_op;             /* SLM_COARSE_MODIFIED, or SLM_COARSE_REDISC (SLM_FP64 only,
+                                  no adjoint, not in a batch) */
 } slm_desc;
 
 typedef struct slm_plan slm_plan;

@@ -35,7 +35,7 @@ class Desc(C.Structure):
                 ("max_levels", C.c_int), ("coarsest_max_points", C.c_int),
                 ("relax", C.c_int), ("gmres_kmax", C.c_int), ("gmres_rtol", C.c_double),
                 ("tol", C.c_double), ("tol_mode", C.c_int), ("max_iter", C.c_int),
-                ("precision", C.c_int), ("adjoint", C.c_int)]
+                ("precision", C.c_int), ("adjoint", C.c_int), ("coarse_op", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -118,5 +118,6 @@ def make_desc(pr, sv, precision: str, adjoint: bool = False):
     d = Desc(pr.dim, pr.nx, pr.nt, float(pr.dt), pr.p, pr.r, keep.a, len(pr.alpha),
              keep.b, len(pr.beta or []), keep.m, len(sv.m), sv.max_levels, sv.coarsest_max_points,
              {"F": 0, "FCF": 1}[sv.relax], sv.gmres_kmax, float(sv.gmres_rtol), float(sv.tol),
-             {"abs": 0, "rel": 1}[sv.tol_mode], sv.max_iter, {"fp64": 0, "fp32": 1}[precision], int(bool(adjoint)))
+             {"abs": 0, "rel": 1}[sv.tol_mode], sv.max_iter, {"fp64": 0, "fp32": 1}[precision], int(bool(adjoint)),
+             {"modified": 0, "ideal": 1, "redisc": 2}[sv.coarse_op])
     return d, keep

@@ -688,6 +688,8 @@ int slm_batch_create(const slm_desc *descs, int n, slm_batch **out)
         if (d.dim != 1 || d.precision != descs[0].precision || d.relax != descs[0].relax)
             return drop(SLM_EUNSUPPORTED, "a batch holds 1D problems of one precision and one relax type");
         if (d.p % 2 == 0) return drop(SLM_EUNSUPPORTED, "a batch needs odd p");
+        if (d.coarse_op != SLM_COARSE_MODIFIED || d.adjoint)
+            return drop(SLM_EUNSUPPORTED, "a batch uses the modified coarse operator and no adjoint");
         slm_plan *P = nullptr;
         const int rc = slm_plan_create(&d, &P);
         if (rc) return drop(rc, "");

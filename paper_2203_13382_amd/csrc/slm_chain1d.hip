@@ -113,7 +113,8 @@ hipError_t launch_chain_1d(const slm_plan &P, int level, int nchains, const Chai
 {
     if (nchains <= 0) return hipSuccess;
     const bool f32 = P.d.precision == SLM_FP32_BULK;
-    if (level > 0) return f32 ? coarse_p<float>(a, nchains, st) : coarse_p<double>(a, nchains, st);
+    if (level > 0 && P.d.coarse_op != SLM_COARSE_REDISC)
+        return f32 ? coarse_p<float>(a, nchains, st) : coarse_p<double>(a, nchains, st);
     // double-buffer the slice when two copies fit in the workgroup's LDS
     const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
     const bool dbuf = 2ull * a.nx * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();

@@ -541,6 +541,11 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             e = launch_stepT(P, 0, nch, (const double *)bufs[cur], S, (double *)bufs[cur ^ 1], S, n_first0 + k,
                              a.stride_chain, 1, (const double *)a.G, (double *)vo, st);
             if (e != hipSuccess) return e;
+        } else if (level > 0 && P.d.coarse_op == SLM_COARSE_REDISC) {
+            // rediscretized coarse operator: a plain SL step at the level's departure points
+            e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S, (const double *)ws_at(P, L.disp),
+                                       plane, nx, n_first0 + k, a.stride_chain, (const T *)a.G, vo);
+            if (e != hipSuccess) return e;
         } else if (level == 0) {
             if (P.d.precision == SLM_FP32_BULK)
                 e = launch_step0<T, float>(P, nch, st, bufs[cur], S, bufs[cur ^ 1], S, (const float *)ws_at(P, L.disp),

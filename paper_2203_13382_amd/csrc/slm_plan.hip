@@ -309,6 +309,10 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
     if (d->max_iter < 1) return fail(nullptr, SLM_EINVAL, "max_iter >= 1 required");
     if (d->precision != SLM_FP64 && d->precision != SLM_FP32_BULK) return fail(nullptr, SLM_EINVAL, "bad precision");
     if (d->adjoint != 0 && d->adjoint != 1) return fail(nullptr, SLM_EINVAL, "adjoint must be 0 or 1");
+    if (d->coarse_op != SLM_COARSE_MODIFIED && d->coarse_op != SLM_COARSE_REDISC)
+        return fail(nullptr, SLM_EUNSUPPORTED, "coarse_op must be SLM_COARSE_MODIFIED or SLM_COARSE_REDISC");
+    if (d->coarse_op == SLM_COARSE_REDISC && (d->precision != SLM_FP64 || d->adjoint))
+        return fail(nullptr, SLM_EUNSUPPORTED, "the rediscretized coarse operator needs SLM_FP64 and no adjoint");
     if (d->adjoint && (d->precision != SLM_FP64 || d->p % 2 == 0))
         return fail(nullptr, SLM_EUNSUPPORTED, "the adjoint needs SLM_FP64 and odd p");
     if (d->adjoint && d->n_alpha + (d->dim == 2 ? d->n_beta : 0) > 16)
@@ -341,7 +345,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
         P->L = l + 2;
     }
     P->lv[P->L - 1].m = 0;
-    if (P->L > 1 && (d->p % 2) == 0) {
+    if (P->L > 1 && (d->p % 2) == 0 && d->coarse_op == SLM_COARSE_MODIFIED) {
         delete P;
         return fail(nullptr, SLM_EUNSUPPORTED, "MGRIT with the modified coarse operator needs odd p");
     }
@@ -447,7 +451,10 @@ int slm_plan_setup(slm_plan *P, void *d_ws, size_t bytes, void *stream)
     P->ready = false;
     P->adj_ready = false;                   // the inverse stencil index follows the departure points
     HIPCHK(P->d.dim == 1 ? launch_trace_1d(*P, st) : launch_trace_2d(*P, st));
-    for (int l = 1; l < P->L; ++l) HIPCHK(P->d.dim == 1 ? launch_backtrack_1d(*P, l, st) : launch_backtrack_2d(*P, l, st));
+    for (int l = 1; l < P->L; ++l) {
+        if (P->d.coarse_op == SLM_COARSE_REDISC) HIPCHK(launch_trace_redisc(*P, l, st));
+        else HIPCHK(P->d.dim == 1 ? launch_backtrack_1d(*P, l, st) : launch_backtrack_2d(*P, l, st));
+    }
     P->ready = true;
     return SLM_OK;
 }

@@ -143,6 +143,30 @@ __global__ void backtrack2d_kernel(int nx, int m, int Nl, int p, const double *_
     scur[plane_cur + (long long)n * S + id] = ay + sgn * (fpoly_odd(p, Dy - floor(Dy)) - fsy);
 }
 
+// Rediscretized coarse operator (Sec. 2.3): the departure point of a level-l
+// step of size M dt (M = m^l fine steps) traced through the M fine-size ERK
+// steps it spans, the position carried from one to the next (unwrapped).
+template <int R, int DIM>
+__global__ void trace_redisc_kernel(int nx, long long S, int Nl, int M, double dt, double h, WaveField fa,
+                                    WaveField fb, double *out)
+{
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = blockIdx.y;
+    if (id >= S || n >= Nl) return;
+    int i, jy;
+    split_xy(id, nx, i, jy);
+    const double x0 = -1.0 + i * h, y0 = DIM == 2 ? -1.0 + jy * h : 0.0;
+    double x = x0, y = y0;
+    for (int s = M - 1; s >= 0; --s) {
+        double dx, dy;
+        erk_back<R, DIM>(fa, fb, x, y, ((double)n * M + s + 1) * dt, dt, h, dx, dy);
+        x -= dx * h;
+        if (DIM == 2) y -= dy * h;
+    }
+    out[(long long)n * S + id] = (x0 - x) / h;
+    if (DIM == 2) out[(long long)Nl * S + (long long)n * S + id] = (y0 - y) / h;
+}
+
 template <int DIM>
 hipError_t trace_dispatch(const slm_plan &P, hipStream_t st)
 {
@@ -173,6 +197,24 @@ const double *setup_disp(const slm_plan &P, int l)
 
 hipError_t launch_trace_1d(const slm_plan &P, hipStream_t st) { return trace_dispatch<1>(P, st); }
 hipError_t launch_trace_2d(const slm_plan &P, hipStream_t st) { return trace_dispatch<2>(P, st); }
+
+hipError_t launch_trace_redisc(const slm_plan &P, int l, hipStream_t st)
+{
+    int M = 1;
+    for (int k = 0; k < l; ++k) M *= P.lv[k].m;
+    const LevelInfo &cur = P.lv[l];
+    const double h = 2.0 / P.d.nx;
+    dim3 grid((unsigned)((P.S + 255) / 256), (unsigned)cur.N);
+    double *out = (double *)ws_at(P, cur.disp);
+#define RD(RR, DD) hipLaunchKernelGGL((trace_redisc_kernel<RR, DD>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, \
+                                      cur.N, M, P.d.dt, h, P.fa, P.fb, out)
+#define RDR(DD) switch (P.d.r) { case 1: RD(1, DD); break; case 2: RD(2, DD); break; case 3: RD(3, DD); break; \
+                                 case 4: RD(4, DD); break; default: RD(5, DD); break; }
+    if (P.d.dim == 1) RDR(1) else RDR(2)
+#undef RDR
+#undef RD
+    return hipGetLastError();
+}
 
 hipError_t launch_backtrack_1d(const slm_plan &P, int l, hipStream_t st)
 {

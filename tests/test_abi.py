@@ -147,3 +147,25 @@ def test_batch_create_rejects_unsupported():
     assert L.slm_batch_create(arr, 0, C.byref(h)) == -1
     assert L.slm_batch_setup(None, None, 0, None) == -1
     assert L.slm_batch_solve(None, None, None, None, None, 0, 0, None) == -1
+
+
+def test_redisc_descriptor_validation():
+    """The rediscretized coarse operator is FP64-only and has no adjoint;
+    unknown coarse operators are rejected before any device call."""
+    import dataclasses
+    L = N.lib()
+    pr = W.Problem(1, 64, 32, 0.05, 3, 3, W.alpha_cfg12())
+    h = C.c_void_p()
+    for sv, prec, adj, rc in [(W.Solver(m=[4], coarse_op="redisc"), "fp32", False, -2),
+                              (W.Solver(m=[4], coarse_op="redisc"), "fp64", True, -2),
+                              (W.Solver(m=[4], coarse_op="ideal"), "fp64", False, -2),
+                              (W.Solver(m=[4], coarse_op="redisc"), "fp64", False, 0)]:
+        d, k = N.make_desc(pr, sv, prec, adj)
+        got = L.slm_plan_create(C.byref(d), C.byref(h))
+        assert got == rc, (sv.coarse_op, prec, adj, got)
+        if got == 0:
+            L.slm_plan_destroy(h)
+    # even p is allowed with the rediscretized operator (no D_{p+1} correction)
+    d, k = N.make_desc(dataclasses.replace(pr, p=2), W.Solver(m=[4], coarse_op="redisc"), "fp64")
+    assert L.slm_plan_create(C.byref(d), C.byref(h)) == 0
+    L.slm_plan_destroy(h)
