@@ -58,7 +58,7 @@ enum { SLM_COARSE_MODIFIED = 0, SLM_COARSE_REDISC = 2 };
 enum {
     SLM_OK = 0,                /* success / converged */
     SLM_NOT_CONVERGED = 1,     /* max_iter cycles without meeting tol */
-    SLM_DIVERGED = 2,          /* residual norm non-finite or > 1e3 rho_0 */
+    SLM_DIVERGED = 2,          /* residual norm not finite (no growth test) */
     SLM_STAGNATED = 3,         /* FP32 bulk: ratio > 0.95 for 3 cycles */
     SLM_EINVAL = -1,           /* invalid argument or descriptor */
     SLM_EUNSUPPORTED = -2,     /* valid but not supported by this build */

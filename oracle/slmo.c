@@ -779,7 +779,11 @@ static void cycle_from(slmo_ctx *c, int l)
  * ...); iterations stop at the first k with rho_k < tol*rho_0 (relative) or
  * rho_k < tol (absolute), and the iteration count is k+1, the number of
  * cycles begun (this count reproduces the constant-speed columns of Tables
- * 1-3).  DIVERGED if rho_k is not finite or exceeds 1e3*rho_0;
+ * 1-3).  DIVERGED only if rho_k is not finite: there is no test on growth,
+ * since with the rediscretised coarse operator of Table 3 the residual
+ * grows by many orders of magnitude and still converges in the printed
+ * number of cycles (rounding added at the peak is damped like any other
+ * error of the iterate);
  * NOT_CONVERGED once k reaches max_iter. */
 int slmo_mgrit(slmo_ctx *c, const double *u0, double *u, double *hist, int hist_cap,
                slmo_stats *st)
@@ -810,7 +814,7 @@ int slmo_mgrit(slmo_ctx *c, const double *u0, double *u, double *hist, int hist_
             s.iterations = k + 1;
             double thr = c->sv.tol_mode == SLMO_TOL_REL ? c->sv.tol * rho0 : c->sv.tol;
             if (rho < thr || rho == 0.0) { s.status = SLMO_CONVERGED; break; }
-            if (!isfinite(rho) || rho > 1e3 * rho0) { s.status = SLMO_DIVERGED; break; }
+            if (!isfinite(rho)) { s.status = SLMO_DIVERGED; break; }
             if (k >= c->sv.max_iter) { s.status = SLMO_NOT_CONVERGED; break; }
             coarse_correct(c, 0);
             f_relax(c, 0);

@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(CTL_THREADS) batch_control(BCtl *ctl, int hist
     const double thr = c.tol_mode == SLM_TOL_REL ? c.tol * c.rho0 : c.tol;
     int stop = 1;
     if (rho < thr || rho == 0.0) c.status = SLM_OK;
-    else if (!isfinite(rho) || rho > 1e3 * c.rho0) c.status = SLM_DIVERGED;
+    else if (!isfinite(rho)) c.status = SLM_DIVERGED;
     else if (c.fp32 && k > 0 && (c.stag = rho > 0.95 * c.prev ? c.stag + 1 : 0) >= 3) c.status = SLM_STAGNATED;
     else if (k >= c.max_iter) c.status = SLM_NOT_CONVERGED;
     else stop = 0;

@@ -217,7 +217,7 @@ int solve_core(slm_plan *P, const void *d_u0, void *d_u, void *d_c, slm_stats *s
             const double thr = P->d.tol_mode == SLM_TOL_REL ? P->d.tol * rho0 : P->d.tol;
             bool stop = true;
             if (rho < thr || rho == 0.0) s.status = SLM_OK;
-            else if (!std::isfinite(rho) || rho > 1e3 * rho0) s.status = SLM_DIVERGED;
+            else if (!std::isfinite(rho)) s.status = SLM_DIVERGED;
             else if (P->d.precision == SLM_FP32_BULK && k > 0 && (stag = rho > 0.95 * prev ? stag + 1 : 0) >= 3)
                 s.status = SLM_STAGNATED;
             else if (k >= P->d.max_iter) s.status = SLM_NOT_CONVERGED;
