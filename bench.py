@@ -288,7 +288,7 @@ def measured_traffic():
     import hashlib
     prof = os.path.join(ROOT, "profiles", "cfg2_kernels.md")
     csrc = os.path.join(ROOT, "paper_2203_13382_amd", "csrc")
-    srcs = [os.path.join(csrc, f) for f in ("slm_kernels1d.h", "slm_chain1d.hip", "slm_common.h")]
+    srcs = [os.path.join(csrc, f) for f in ("slm_kernels1d.h", "slm_chain1d.hip", "slm_fine1d.hip", "slm_common.h")]
     try:
         kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
                   and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"))

@@ -379,8 +379,8 @@ hipError_t fine_launch(const slm_batch &B, const slm_batch::Op &o, hipStream_t s
     const BItem *items = (const BItem *)(B.ws + o.off);
     const BCtl *ctl = (const BCtl *)(B.ws + B.o_ctl);
     const long long nxg = o.maxelems;
-    const bool dbuf = 2ull * nxg * sizeof(T) + SLM_RED_DOUBLES * sizeof(double) + 16 <= (size_t)lds_cap();
-    const size_t lds = (((size_t)(dbuf ? 2 : 1) * nxg * sizeof(T) + 15) & ~size_t(15)) +
+    const bool dbuf = 2ull * fine_slice_len((int)nxg) * sizeof(T) + SLM_RED_DOUBLES * sizeof(double) + 16 <= (size_t)lds_cap();
+    const size_t lds = (((size_t)(dbuf ? 2 : 1) * fine_slice_len((int)nxg) * sizeof(T) + 15) & ~size_t(15)) +
                        SLM_RED_DOUBLES * sizeof(double);
     const int grid = std::max(1, std::min(o.n, B.grid_mult * B.cus * (SLM_MAXB / o.block)));
     const int block = o.block;

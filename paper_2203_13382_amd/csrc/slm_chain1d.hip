@@ -8,7 +8,8 @@
 // (and the right-hand side on coarse levels) plus the slices a sweep writes.
 //
 // Level 0 applies the semi-Lagrangian step of Sec. 2.1; its kernel streams
-// the displacements through a prefetch ring PF steps deep.  Coarse levels
+// the displacements through a prefetch ring PF steps deep (launchers in
+// slm_fine1d.hip, a translation unit of its own).  Coarse levels
 // apply the modified operator of eq. (Phi_multilevel),
 //     v <- [I - diag(sigma) D_{p+1}]^{-1} S_{p,r*} v,
 // with the inverse applied by GMRES inside the workgroup (Sec. 3.3 / 3.4):
@@ -44,34 +45,6 @@ hipError_t launch(K kern, int nchains, int block, size_t lds, const ChainArgs &a
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(nchains), dim3(block), lds, st, a);
     return hipGetLastError();
-}
-
-template <typename T, typename TD, int P, bool DBUF>
-hipError_t fine_ept(const ChainArgs &a, int nchains, hipStream_t st)
-{
-    const int block = fine_block(a.nx, nchains);
-    const int ept = (a.nx + block - 1) / block;
-    const size_t lds = (((size_t)(DBUF ? 2 : 1) * a.nx * sizeof(T) + 15) & ~size_t(15)) +
-                       SLM_RED_DOUBLES * sizeof(double);
-    switch (ept) {
-    case 1: return launch(fine1d<T, TD, P, 1, DBUF, pf_depth<TD, 1>()>, nchains, block, lds, a, st);
-    case 2: return launch(fine1d<T, TD, P, 2, DBUF, pf_depth<TD, 2>()>, nchains, block, lds, a, st);
-    case 3:
-    case 4: return launch(fine1d<T, TD, P, 4, DBUF, pf_depth<TD, 4>()>, nchains, block, lds, a, st);
-    default: return launch(fine1d<T, TD, P, 8, DBUF, pf_depth<TD, 8>()>, nchains, block, lds, a, st);
-    }
-}
-
-template <typename T, typename TD, bool DBUF>
-hipError_t fine_p(const ChainArgs &a, int nchains, hipStream_t st)
-{
-    switch (a.p) {
-    case 1: return fine_ept<T, TD, 1, DBUF>(a, nchains, st);
-    case 2: return fine_ept<T, TD, 2, DBUF>(a, nchains, st);
-    case 3: return fine_ept<T, TD, 3, DBUF>(a, nchains, st);
-    case 4: return fine_ept<T, TD, 4, DBUF>(a, nchains, st);
-    default: return fine_ept<T, TD, 5, DBUF>(a, nchains, st);
-    }
 }
 
 template <typename T, int P, int EPT>
@@ -115,9 +88,5 @@ hipError_t launch_chain_1d(const slm_plan &P, int level, int nchains, const Chai
     const bool f32 = P.d.precision == SLM_FP32_BULK;
     if (level > 0 && P.d.coarse_op != SLM_COARSE_REDISC)
         return f32 ? coarse_p<float>(a, nchains, st) : coarse_p<double>(a, nchains, st);
-    // double-buffer the slice when two copies fit in the workgroup's LDS
-    const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
-    const bool dbuf = 2ull * a.nx * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
-    if (f32) return dbuf ? fine_p<float, float, true>(a, nchains, st) : fine_p<float, float, false>(a, nchains, st);
-    return dbuf ? fine_p<double, double, true>(a, nchains, st) : fine_p<double, double, false>(a, nchains, st);
+    return launch_fine_1d(nchains, f32, a, st);
 }

@@ -1,0 +1,76 @@
+// slm_fine1d.hip -- launchers of the level-0 sweep and sequential-stepping
+// kernels of the 1D path (Sec. 2.1 steps, chained per coarse interval as in
+// Sec. 2.2).  The kernels live in slm_kernels1d.h; this unit only chooses
+// the instantiation: elements per thread, double buffering, prefetch depth,
+// and the fast variant for slices that fill the workgroup exactly and whose
+// displacements need a one-sided wrap only.
+#include "slm_kernels1d.h"
+
+namespace {
+
+using namespace slmk;
+
+// ------------------------------------------------------------------ launchers
+int lds_limit()
+{
+    static int v = -1;
+    if (v < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+    }
+    return v;
+}
+
+template <typename K>
+hipError_t launch(K kern, int nchains, int block, size_t lds, const ChainArgs &a, hipStream_t st)
+{
+    if (lds > (size_t)lds_limit()) return hipErrorInvalidConfiguration;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nchains), dim3(block), lds, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, typename TD, int P, bool DBUF>
+hipError_t fine_ept(const ChainArgs &a, int nchains, hipStream_t st)
+{
+    const int block = fine_block(a.nx, nchains);
+    const int ept = (a.nx + block - 1) / block;
+    const size_t lds = (((size_t)(DBUF ? 2 : 1) * fine_slice_len(a.nx) * sizeof(T) + 15) & ~size_t(15)) +
+                       SLM_RED_DOUBLES * sizeof(double);
+#define FL(E) (a.nx == (E) * block ? launch(fine1d<T, TD, P, E, DBUF, pf_depth<TD, E>(), true>, nchains, block, lds, a, st) \
+                                   : launch(fine1d<T, TD, P, E, DBUF, pf_depth<TD, E>(), false>, nchains, block, lds, a, st))
+    switch (ept) {
+    case 1: return FL(1);
+    case 2: return FL(2);
+    case 3:
+    case 4: return FL(4);
+    default: return FL(8);
+    }
+#undef FL
+}
+
+template <typename T, typename TD, bool DBUF>
+hipError_t fine_p(const ChainArgs &a, int nchains, hipStream_t st)
+{
+    switch (a.p) {
+    case 1: return fine_ept<T, TD, 1, DBUF>(a, nchains, st);
+    case 2: return fine_ept<T, TD, 2, DBUF>(a, nchains, st);
+    case 3: return fine_ept<T, TD, 3, DBUF>(a, nchains, st);
+    case 4: return fine_ept<T, TD, 4, DBUF>(a, nchains, st);
+    default: return fine_ept<T, TD, 5, DBUF>(a, nchains, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fine_1d(int nchains, bool f32, const ChainArgs &a, hipStream_t st)
+{
+    // double-buffer the slice when two copies fit in the workgroup's LDS
+    const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
+    const bool dbuf = 2ull * fine_slice_len(a.nx) * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
+    if (f32) return dbuf ? fine_p<float, float, true>(a, nchains, st) : fine_p<float, float, false>(a, nchains, st);
+    return dbuf ? fine_p<double, double, true>(a, nchains, st) : fine_p<double, double, false>(a, nchains, st);
+}

@@ -92,6 +92,7 @@ hipError_t launch_trace_1d(const slm_plan &P, hipStream_t st);
 hipError_t launch_backtrack_1d(const slm_plan &P, int level, hipStream_t st);
 hipError_t launch_trace_redisc(const slm_plan &P, int level, hipStream_t st);
 hipError_t launch_chain_1d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);
+hipError_t launch_fine_1d(int nchains, bool f32, const ChainArgs &a, hipStream_t st);
 hipError_t launch_trace_2d(const slm_plan &P, hipStream_t st);
 hipError_t launch_backtrack_2d(const slm_plan &P, int level, hipStream_t st);
 hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);

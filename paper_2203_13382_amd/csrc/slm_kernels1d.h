@@ -51,6 +51,47 @@ __device__ __forceinline__ T interp1(const T *__restrict__ s, int i, TD d, int n
     return acc;
 }
 
+// Level-0 slices in LDS carry a periodic tail: entries nx .. nx+SLM_SLICE_PAD-1
+// repeat nodes 0, 1, ... (mod nx), so the p+1 taps of a stencil that starts
+// inside the slice are read at base, base+1, ... without a per-tap wrap.
+constexpr int SLM_SLICE_PAD = 8;
+__host__ __device__ inline size_t fine_slice_len(int nx) { return (size_t)nx + SLM_SLICE_PAD; }
+
+// interp1 on a padded slice: one wrap of the stencil start, then p+1
+// consecutive LDS reads (same products and summation order as interp1).
+template <int P, typename T, typename TD>
+__device__ __forceinline__ T interp1_padded(const T *__restrict__ s, int i, TD d, int nx, int nsmall)
+{
+    static_assert(P < SLM_SLICE_PAD, "the periodic tail must cover p taps past the last node");
+    const TD fl = floor(d);
+    const T eps = T(d - fl);
+    const int first = stencil_first<T>(P, eps);
+    int base = i - int(fl) + first;
+    if (nsmall) {
+        base += base < 0 ? nx : 0;
+        base -= base >= nx ? nx : 0;
+    } else {
+        base = wrap_mod(base, nx);
+    }
+    T w[P + 1];
+    lagrange_weights<P, T>(-eps - T(first), w);
+    const T *sp = s + base;
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j <= P; ++j) acc += w[j] * sp[j];
+    return acc;
+}
+
+// Write the periodic tail of a padded slice from the registers that hold
+// nodes 0 .. nx-1 in the strided layout (thread t holds node t in val[0]).
+template <typename T>
+__device__ __forceinline__ void pad_slice(T *sl, T v0, int nx)
+{
+    const int tid = threadIdx.x;
+    if (tid < nx)
+        for (int t = tid; t < SLM_SLICE_PAD; t += nx) sl[nx + t] = v0;
+}
+
 // Load the chain's start slice into LDS (and registers); optionally copy it
 // to the full-iterate output and, for chain 0 of a C-point sweep, to Cout[0].
 template <typename T, int EPT>
@@ -108,14 +149,17 @@ __device__ __forceinline__ void chain_finish(const ChainArgs &a, int j, const T 
 }
 
 // ------------------------------------------------------------------ level 0 (and sequential stepping)
-template <typename T, typename TD, int P, int EPT, bool DBUF, int PF>
+// FAST: nx == EPT * blockDim and a.nsmall (no node guards, one-sided stencil
+// wrap decided at compile time).
+template <typename T, typename TD, int P, int EPT, bool DBUF, int PF, bool FAST = false>
 __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned char *smem)
 {
+    constexpr bool FULL = FAST;
     const int tid = threadIdx.x, B = blockDim.x, nx = a.nx;
     const long long S = a.S;
     T *sl0 = reinterpret_cast<T *>(smem);
-    T *sl1 = DBUF ? sl0 + nx : sl0;
-    const size_t off = ((size_t)(DBUF ? 2 : 1) * nx * sizeof(T) + 15) & ~size_t(15);
+    T *sl1 = DBUF ? sl0 + fine_slice_len(nx) : sl0;
+    const size_t off = ((size_t)(DBUF ? 2 : 1) * fine_slice_len(nx) * sizeof(T) + 15) & ~size_t(15);
     double *red = reinterpret_cast<double *>(smem + off);
     const TD *disp = static_cast<const TD *>(a.disp);
     const T *G = static_cast<const T *>(a.G);
@@ -125,13 +169,14 @@ __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned c
 
     T val[EPT];
     chain_start<T, EPT>(a, j, sl0, val, n_first);
+    pad_slice(sl0, val[0], nx);
     TD ring[PF][EPT];                           // displacements of the next PF steps
 #pragma unroll
     for (int u = 0; u < PF; ++u)
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = tid + e * B;
-            ring[u][e] = (u < ns && i < nx) ? disp[(n_first + u) * S + i] : TD(0);
+            ring[u][e] = (u < ns && (FULL || i < nx)) ? disp[(n_first + u) * S + i] : TD(0);
         }
     __syncthreads();
     int cur = 0;
@@ -141,31 +186,41 @@ __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned c
             const int k = k0 + u;
             if (k >= ns) break;
             const long long n = n_first + k;
-            TD dc[EPT];
+            // Refill for step k+PF into separate registers, issued before
+            // this step's arithmetic and kept there by the scheduling
+            // barrier; the refill is unconditional (the last PF steps
+            // re-read their own row, which is cached), so the loads stay in
+            // straight-line code and are waited for only at their use.
+            const TD *drow = disp + (k + PF < ns ? n + PF : n) * S;   // uniform row base
+            TD nxt[EPT];
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
-                dc[e] = ring[u][e];
                 const int i = tid + e * B;
-                if (k + PF < ns && i < nx) ring[u][e] = disp[(n + PF) * S + i];
+                nxt[e] = (FULL || i < nx) ? drow[i] : TD(0);
             }
+            __builtin_amdgcn_sched_barrier(0);
             const T *src = cur ? sl1 : sl0;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int i = tid + e * B;
-                val[e] = i < nx ? interp1<P, T, TD>(src, i, dc[e], nx, a.nsmall) : T(0);
+                val[e] = (FULL || i < nx) ? interp1_padded<P, T, TD>(src, i, ring[u][e], nx, FAST ? 1 : a.nsmall) : T(0);
+                ring[u][e] = nxt[e];
             }
             if constexpr (!DBUF) __syncthreads();
             T *dst = DBUF ? (cur ? sl0 : sl1) : sl0;
             const bool wv = Vout && (k + 1 < ns || a.write_last);
+            const T *grow = G ? G + (n + 1) * S : nullptr;
+            T *vrow = wv ? Vout + (n + 1) * S : nullptr;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int i = tid + e * B;
-                if (i < nx) {
-                    if (G) val[e] += G[(n + 1) * S + i];
+                if (FULL || i < nx) {
+                    if (grow) val[e] += grow[i];
                     dst[i] = val[e];
-                    if (wv) Vout[(n + 1) * S + i] = val[e];
+                    if (vrow) vrow[i] = val[e];
                 }
             }
+            pad_slice(dst, val[0], nx);
             if (DBUF) cur ^= 1;
             __syncthreads();
         }
@@ -173,11 +228,11 @@ __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned c
     chain_finish<T, EPT>(a, j, val, red, 0);
 }
 
-template <typename T, typename TD, int P, int EPT, bool DBUF, int PF>
+template <typename T, typename TD, int P, int EPT, bool DBUF, int PF, bool FAST>
 __global__ void __launch_bounds__(SLM_MAXB) fine1d(ChainArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    fine_chain<T, TD, P, EPT, DBUF, PF>(a, blockIdx.x, smem);
+    fine_chain<T, TD, P, EPT, DBUF, PF, FAST>(a, blockIdx.x, smem);
 }
 
 // ------------------------------------------------------------------ coarse levels
