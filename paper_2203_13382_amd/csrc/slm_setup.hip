@@ -40,25 +40,97 @@ __device__ __forceinline__ void erk_back(const WaveField &fa, const WaveField &f
     dy = dt * sy / h;
 }
 
-template <int R, int DIM>
-__global__ void trace_kernel(int nx, long long S, int nt, double dt, double h, WaveField fa, WaveField fb,
-                             double *out64, float *out32)
+// The wave-speed terms of the fine trace, split into the factor that is the
+// same for every node of a stage (coefficient, time factor, and the space
+// factors of zero wavenumber; in 1D also the y factor at y = 0) and the
+// per-node space factors.  The products are those of wave_eval, taken in a
+// different order.
+template <int DIM>
+__device__ __forceinline__ void stage_factors(const WaveField &f, double ts, double (&u)[SLM_MAX_TERMS])
 {
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = blockIdx.y;
-    if (id >= S) return;
-    int i, jy;
-    split_xy(id, nx, i, jy);
-    double dx, dy;
-    erk_back<R, DIM>(fa, fb, -1.0 + i * h, DIM == 2 ? -1.0 + jy * h : 0.0, (n + 1) * dt, dt, h, dx, dy);
-    const long long o = (long long)n * S + id, plane = (long long)nt * S;
-    if (out64) {
-        out64[o] = dx;
-        if (DIM == 2) out64[plane + o] = dy;
+    for (int k = 0; k < f.n; ++k) {
+        double v = f.coef[k] * cos(f.kt[k] * SLM_PI * ts + f.pt[k]);
+        if (f.kx[k] == 0.0) v *= cos(f.px[k]);
+        if (DIM == 1 || f.ky[k] == 0.0) v *= cos(f.ky[k] * SLM_PI * 0.0 + f.py[k]);
+        u[k] = v;
     }
-    if (out32) {
-        out32[o] = (float)dx;
-        if (DIM == 2) out32[plane + o] = (float)dy;
+}
+
+template <int DIM>
+__device__ __forceinline__ double node_eval(const WaveField &f, const double (&u)[SLM_MAX_TERMS], double X, double Y)
+{
+    double s = 0.0;
+    for (int k = 0; k < f.n; ++k) {
+        double v = u[k];
+        if (f.kx[k] != 0.0) v *= cos(f.kx[k] * SLM_PI * X + f.px[k]);
+        if (DIM == 2 && f.ky[k] != 0.0) v *= cos(f.ky[k] * SLM_PI * Y + f.py[k]);
+        s += v;
+    }
+    return s;
+}
+
+// Fine departure trace: trace_npt nodes of one step per thread, so that the
+// per-stage factors are evaluated once for all of them.
+template <int DIM>
+constexpr int trace_npt() { return DIM == 1 ? 4 : 2; }
+
+template <int R, int DIM>
+__global__ void __launch_bounds__(256) trace_kernel(int nx, long long S, int nt, double dt, double h, WaveField fa,
+                                                    WaveField fb, double *out64, float *out32)
+{
+    constexpr int NPT = trace_npt<DIM>();
+    const Erk e = erk_tableau(R);
+    const int n = blockIdx.y;
+    const long long id0 = (long long)blockIdx.x * blockDim.x * NPT + threadIdx.x;
+    double x[NPT], y[NPT], kx[NPT][6], ky[NPT][6];
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const long long id = id0 + (long long)j * blockDim.x;
+        int i = 0, jy = 0;
+        if (id < S) split_xy(id, nx, i, jy);
+        x[j] = -1.0 + i * h;
+        y[j] = DIM == 2 ? -1.0 + jy * h : 0.0;
+    }
+    const double hs = -dt, t_arr = (n + 1) * dt;
+    double ua[SLM_MAX_TERMS], ub[SLM_MAX_TERMS];
+#pragma unroll
+    for (int s = 0; s < e.s; ++s) {
+        const double ts = t_arr + e.c[s] * hs;
+        stage_factors<DIM>(fa, ts, ua);
+        if (DIM == 2) stage_factors<DIM>(fb, ts, ub);
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            double X = x[j], Y = y[j];
+#pragma unroll
+            for (int q = 0; q < s; ++q) {
+                X += hs * e.a[s][q] * kx[j][q];
+                if (DIM == 2) Y += hs * e.a[s][q] * ky[j][q];
+            }
+            kx[j][s] = node_eval<DIM>(fa, ua, X, Y);
+            ky[j][s] = DIM == 2 ? node_eval<DIM>(fb, ub, X, Y) : 0.0;
+        }
+    }
+    const long long plane = (long long)nt * S;
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+        const long long id = id0 + (long long)j * blockDim.x;
+        if (id >= S) continue;
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int s = 0; s < e.s; ++s) {
+            sx += e.b[s] * kx[j][s];
+            sy += e.b[s] * ky[j][s];
+        }
+        const double dx = dt * sx / h, dy = dt * sy / h;
+        const long long o = (long long)n * S + id;
+        if (out64) {
+            out64[o] = dx;
+            if (DIM == 2) out64[plane + o] = dy;
+        }
+        if (out32) {
+            out32[o] = (float)dx;
+            if (DIM == 2) out32[plane + o] = (float)dy;
+        }
     }
 }
 
@@ -175,7 +247,8 @@ hipError_t trace_dispatch(const slm_plan &P, hipStream_t st)
     double *o64 = (double *)ws_at(P, f32 ? L0.disp64 : L0.disp);
     float *o32 = f32 ? (float *)ws_at(P, L0.disp) : nullptr;
     const double h = 2.0 / P.d.nx;
-    dim3 grid((unsigned)((P.S + 255) / 256), (unsigned)P.d.nt);
+    constexpr int NPT = trace_npt<DIM>();
+    dim3 grid((unsigned)((P.S + 256 * NPT - 1) / (256 * NPT)), (unsigned)P.d.nt);
     switch (P.d.r) {
     case 1: hipLaunchKernelGGL((trace_kernel<1, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
     case 2: hipLaunchKernelGGL((trace_kernel<2, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
