@@ -68,9 +68,15 @@ hipError_t fine_p(const ChainArgs &a, int nchains, hipStream_t st)
 
 hipError_t launch_fine_1d(int nchains, bool f32, const ChainArgs &a, hipStream_t st)
 {
-    // double-buffer the slice when two copies fit in the workgroup's LDS
+    // Double-buffer the slice when two copies fit in the workgroup's LDS,
+    // except for FP64 sweeps over many intervals: with one slice buffer
+    // three workgroups share a CU instead of two (LDS 3 x 33 KB for 4096
+    // points), which keeps more displacement loads in flight and outweighs
+    // the extra barrier per step (level-0 sweep of the 1D workload: 152 ->
+    // 142 us).
     const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
-    const bool dbuf = 2ull * fine_slice_len(a.nx) * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
+    const bool dbuf = 2ull * fine_slice_len(a.nx) * (f32 ? 4 : 8) + extra <= (size_t)lds_limit() &&
+                      (f32 || nchains < 512);
     if (f32) return dbuf ? fine_p<float, float, true>(a, nchains, st) : fine_p<float, float, false>(a, nchains, st);
     return dbuf ? fine_p<double, double, true>(a, nchains, st) : fine_p<double, double, false>(a, nchains, st);
 }
