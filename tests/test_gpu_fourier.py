@@ -1,0 +1,42 @@
+"""Convergence factors of two-level FCF MGRIT on the GPU for constant wave
+speed (alpha = 1, nx = 128, nt = 2^14, 10 GMRES iterations with rtol 0, as
+for the measured points of Figs. 2 and 3) against the Fourier estimate of
+eq. (rho_MGRIT_asym): the factor of the last cycle lies within 20% below
+and 5% above the estimate, and above 1 where the estimate is."""
+import numpy as np
+import pytest
+
+from paper_2203_13382_amd import fourier as F
+from paper_2203_13382_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+@pytest.mark.parametrize("p,c,m,coarse", [(1, 0.8, 4, "modified"), (3, 0.8, 4, "modified"),
+                                          (3, 0.6, 8, "modified"), (1, 0.9, 4, "redisc"),
+                                          (1, 0.62, 2, "redisc")])
+def test_measured_factor_matches_estimate(torch, p, c, m, coarse):
+    from paper_2203_13382_amd import Plan
+    nx, nt = 128, 2 ** 14
+    pr = W.Problem(1, nx, nt, c * 2.0 / nx, p, p, [W.term(1.0)], [])
+    sv = W.Solver(m=[m], max_levels=2, gmres_kmax=10, gmres_rtol=0.0, max_iter=30, coarse_op=coarse)
+    plan = Plan(pr, sv, "fp64").setup()
+    u0 = np.sin(np.pi * (-1.0 + np.arange(nx) * 2.0 / nx)) ** 4
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    cpts = torch.rand((plan.n_cpoints, nx), generator=g, dtype=torch.float64, device="cuda")
+    st, hist = plan.solve_cpoints(torch.from_numpy(u0), cpts)
+    fac = hist[-1] / hist[-2]
+    est = F.rho(p, c, m, coarse)
+    print(f"p={p} c={c} m={m} {coarse}: measured {fac:.4f}, estimate {est:.4f}, "
+          f"{st['iterations']} cycles ({st['status']})", flush=True)
+    assert 0.8 * est <= fac <= 1.05 * est, (fac, est)
+    if est > 1:
+        assert fac > 1
