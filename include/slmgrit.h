@@ -50,10 +50,13 @@ enum { SLM_RELAX_F = 0, SLM_RELAX_FCF = 1 };            /* Sec. 2.2 */
 enum { SLM_TOL_ABS = 0, SLM_TOL_REL = 1 };
 enum { SLM_FP64 = 0, SLM_FP32_BULK = 1 };
 /* Coarse-grid operator: the modified SL operator of eq. (Phi_multilevel) /
- * (BEOper_2D), or the rediscretized SL operator of Sec. 2.3 (a plain SL
- * step of size m^l dt whose departure points are traced through the m^l
- * fine-size ERK steps it spans, as in Sec. 4.3's comparison). */
-enum { SLM_COARSE_MODIFIED = 0, SLM_COARSE_REDISC = 2 };
+ * (BEOper_2D), the rediscretized SL operator of Sec. 2.3 (a plain SL step of
+ * size m^l dt whose departure points are traced through the m^l fine-size
+ * ERK steps it spans, as in Sec. 4.3's comparison), or the explicit
+ * forward-Euler operator of eq. (Fp_def), [I + diag(sigma) D_{p+1}] S_{p,r*}
+ * with the same departure points and sigma as the modified operator (the
+ * paper finds it unstable for larger m, Sec. 3.2). */
+enum { SLM_COARSE_MODIFIED = 0, SLM_COARSE_REDISC = 2, SLM_COARSE_FWD_EULER = 3 };
 
 enum {
     SLM_OK = 0,                /* success / converged */
@@ -90,8 +93,9 @@ typedef struct {
     int precision;             /* SLM_FP64 or SLM_FP32_BULK */
     int adjoint;               /* 1: also size the workspace for slm_adjoint (needs SLM_FP64,
                                   odd p and at least two levels); 0: forward only */
-    int coarse_op;             /* SLM_COARSE_MODIFIED, or SLM_COARSE_REDISC (SLM_FP64 only,
-                                  no adjoint, not in a batch) */
+    int coarse_op;             /* SLM_COARSE_MODIFIED; SLM_COARSE_REDISC (SLM_FP64 only, no
+                                  adjoint, not in a batch); SLM_COARSE_FWD_EULER (odd p,
+                                  SLM_FP64 only, no adjoint, not in a batch) */
 } slm_desc;
 
 typedef struct slm_plan slm_plan;

@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "slmo.c")
 LIB = os.path.join(HERE, "libslmo.so")
 
 RELAX = {"F": 0, "FCF": 1}
-COARSE = {"modified": 0, "ideal": 1, "redisc": 2}
+COARSE = {"modified": 0, "ideal": 1, "redisc": 2, "fwd_euler": 3}
 TOLMODE = {"abs": 0, "rel": 1}
 STATUS = {0: "converged", 1: "not_converged", 2: "diverged"}
 

@@ -251,6 +251,66 @@ void slmo_apply_D(int nx, int p, const double *v, double *out)
     }
 }
 
+/* out = [I + diag(sx) D_x + diag(sy) D_y] v: the explicit forward-Euler
+ * correction F_{p+1} of eq. (Fp_def), applied after the coarse SL step; the
+ * coefficients are the same phi / sigma as for the backward-Euler operator. */
+void slmo_apply_F(int dim, int nx, int p, const double *sx, const double *sy,
+                  const double *v, double *out)
+{
+    double taps[8];
+    int q = (p + 1) / 2;
+    slmo_dop_taps(p, taps);
+    if (dim == 1) {
+        for (int i = 0; i < nx; i++) {
+            double d = 0.0;
+            for (int k = -q; k <= q; k++) d += taps[k + q] * v[pmod(i + k, nx)];
+            out[i] = v[i] + sx[i] * d;
+        }
+        return;
+    }
+    for (int j = 0; j < nx; j++)
+        for (int i = 0; i < nx; i++) {
+            double dx = 0.0, dy = 0.0;
+            for (int k = -q; k <= q; k++) {
+                dx += taps[k + q] * v[(long long)j * nx + pmod(i + k, nx)];
+                dy += taps[k + q] * v[pmod(j + k, nx) * nx + i];
+            }
+            long long id = (long long)j * nx + i;
+            out[id] = v[id] + sx[id] * dx + sy[id] * dy;
+        }
+}
+
+/* Transpose of slmo_apply_F: out = v + D_x (sx .* v) + D_y (sy .* v). */
+void slmo_apply_FT(int dim, int nx, int p, const double *sx, const double *sy,
+                   const double *v, double *out)
+{
+    double taps[8];
+    int q = (p + 1) / 2;
+    slmo_dop_taps(p, taps);
+    if (dim == 1) {
+        for (int i = 0; i < nx; i++) {
+            double d = 0.0;
+            for (int k = -q; k <= q; k++) {
+                long long t = pmod(i + k, nx);
+                d += taps[k + q] * sx[t] * v[t];
+            }
+            out[i] = v[i] + d;
+        }
+        return;
+    }
+    for (int j = 0; j < nx; j++)
+        for (int i = 0; i < nx; i++) {
+            double dx = 0.0, dy = 0.0;
+            for (int k = -q; k <= q; k++) {
+                long long tx = (long long)j * nx + pmod(i + k, nx), ty = pmod(j + k, nx) * nx + i;
+                dx += taps[k + q] * sx[tx] * v[tx];
+                dy += taps[k + q] * sy[ty] * v[ty];
+            }
+            long long id = (long long)j * nx + i;
+            out[id] = v[id] + dx + dy;
+        }
+}
+
 /* out = [I - diag(sx) D_x - diag(sy) D_y] v: the matrix inverted by the
  * backward-Euler correction, eq. (Phi_multilevel) in 1D and eq. (BEOper_2D)
  * in 2D, with D_x = I (x) D_{p+1} and D_y = D_{p+1} (x) I (Sec. 4.2). */
@@ -649,7 +709,8 @@ const double *slmo_level_sigma(const slmo_ctx *c, int l, int comp) { return c->s
 /* The level-l time-stepper Phi_l for step n (t_n^l -> t_{n+1}^l).
  * l = 0: S_{p,r} (Sec. 2.1).  l >= 1, modified: [I - diag(sigma) D]^{-1}
  * S_{p,r*} (eq. Phi_multilevel; eq. BEOper_2D in 2D) with the inverse
- * approximated by GMRES.  Ideal: the product of the fine steps it spans
+ * approximated by GMRES.  Forward Euler: [I + diag(sigma) D] S_{p,r*}
+ * (eq. Fp_def), explicit.  Ideal: the product of the fine steps it spans
  * (Sec. 2.2).  Rediscretised: S_{p,r} with the coarse time-step. */
 void slmo_apply_phi(slmo_ctx *c, int l, int n, const double *in, double *out)
 {
@@ -676,6 +737,12 @@ void slmo_apply_phi(slmo_ctx *c, int l, int n, const double *in, double *out)
     double *tmp = (double *)malloc(sizeof(double) * S);
     slmo_interp(pr->dim, pr->nx, pr->p, c->dep[l][0] + (long long)n * S,
                 pr->dim == 2 ? c->dep[l][1] + (long long)n * S : NULL, in, tmp);
+    if (c->sv.coarse_op == SLMO_COARSE_FWD) {   /* eq. (Fp_def): explicit correction */
+        slmo_apply_F(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
+                     pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL, tmp, out);
+        free(tmp);
+        return;
+    }
     int it = slmo_bsolve(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
                          pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL,
                          tmp, out, c->sv.gmres_kmax, c->sv.gmres_rtol);
@@ -901,6 +968,14 @@ void slmo_apply_phi_T(slmo_ctx *c, int l, int n, const double *in, double *out)
         return;
     }
     double *tmp = (double *)malloc(sizeof(double) * S);
+    if (c->sv.coarse_op == SLMO_COARSE_FWD) {   /* (F S)^T = S^T F^T */
+        slmo_apply_FT(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
+                      pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL, in, tmp);
+        slmo_interp_T(pr->dim, pr->nx, pr->p, c->dep[l][0] + (long long)n * S,
+                      pr->dim == 2 ? c->dep[l][1] + (long long)n * S : NULL, tmp, out);
+        free(tmp);
+        return;
+    }
     int it = slmo_bsolve_T(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
                            pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL,
                            in, tmp, c->sv.gmres_kmax, c->sv.gmres_rtol);

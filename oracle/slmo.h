@@ -32,7 +32,7 @@ extern "C" {
 typedef struct { double coef, kx, px, ky, py, kt, pt; } slmo_term;
 
 enum { SLMO_RELAX_F = 0, SLMO_RELAX_FCF = 1 };
-enum { SLMO_COARSE_MODIFIED = 0, SLMO_COARSE_IDEAL = 1, SLMO_COARSE_REDISC = 2 };
+enum { SLMO_COARSE_MODIFIED = 0, SLMO_COARSE_IDEAL = 1, SLMO_COARSE_REDISC = 2, SLMO_COARSE_FWD = 3 };
 enum { SLMO_TOL_ABS = 0, SLMO_TOL_REL = 1 };
 enum { SLMO_CONVERGED = 0, SLMO_NOT_CONVERGED = 1, SLMO_DIVERGED = 2 };
 
@@ -77,6 +77,13 @@ void slmo_depart_fine(const slmo_problem *pr, int n, double *xi, double *eta);
 void slmo_interp(int dim, int nx, int p, const double *xi, const double *eta,
                  const double *u, double *out);
 void slmo_apply_D(int nx, int p, const double *v, double *out);
+/* out = [I + diag(sx) D_x + diag(sy) D_y] v: the explicit forward-Euler
+ * correction F_{p+1} of eq. (Fp_def). */
+void slmo_apply_F(int dim, int nx, int p, const double *sx, const double *sy,
+                  const double *v, double *out);
+/* out = [I + D_x diag(sx) + D_y diag(sy)] v (its transpose; D symmetric). */
+void slmo_apply_FT(int dim, int nx, int p, const double *sx, const double *sy,
+                   const double *v, double *out);
 void slmo_apply_B(int dim, int nx, int p, const double *sx, const double *sy,
                   const double *v, double *out);
 int  slmo_bsolve(int dim, int nx, int p, const double *sx, const double *sy,

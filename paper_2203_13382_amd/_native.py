@@ -119,5 +119,5 @@ def make_desc(pr, sv, precision: str, adjoint: bool = False):
              keep.b, len(pr.beta or []), keep.m, len(sv.m), sv.max_levels, sv.coarsest_max_points,
              {"F": 0, "FCF": 1}[sv.relax], sv.gmres_kmax, float(sv.gmres_rtol), float(sv.tol),
              {"abs": 0, "rel": 1}[sv.tol_mode], sv.max_iter, {"fp64": 0, "fp32": 1}[precision], int(bool(adjoint)),
-             {"modified": 0, "ideal": 1, "redisc": 2}[sv.coarse_op])
+             {"modified": 0, "ideal": 1, "redisc": 2, "fwd_euler": 3}[sv.coarse_op])
     return d, keep

@@ -20,6 +20,8 @@
 // coarse workgroups use at most 512 threads to get 256 VGPRs per lane.
 #include "slm_kernels1d.h"
 
+#include <type_traits>
+
 namespace {
 
 using namespace slmk;
@@ -53,6 +55,12 @@ hipError_t coarse_launch(const ChainArgs &a, int nchains, hipStream_t st)
     size_t o1, o2, o3;
     const size_t lds = coarse_lds_parts<T, EPT>(a.nx, &o1, &o2, &o3);
     const int block = ((a.nx + EPT - 1) / EPT + 63) / 64 * 64;
+    if constexpr (std::is_same<T, double>::value) {   // the forward-Euler operator is FP64 only
+        if (a.fwd) {
+            if (a.nx == EPT * block) return launch(coarse1d<T, P, EPT, true, true>, nchains, block, lds, a, st);
+            return launch(coarse1d<T, P, EPT, false, true>, nchains, block, lds, a, st);
+        }
+    }
     if (a.nx == EPT * block) return launch(coarse1d<T, P, EPT, true>, nchains, block, lds, a, st);
     return launch(coarse1d<T, P, EPT, false>, nchains, block, lds, a, st);
 }

@@ -425,6 +425,47 @@ __global__ void __launch_bounds__(TPB) g2_combine(const T *__restrict__ V, long 
     }
 }
 
+// Explicit forward-Euler correction of eq. (Fp_def) on the interpolated
+// slices b (one per chain): dst = b + sx .* (D_x b) + sy .* (D_y b), plus
+// G(n+1), also written to Vout.
+template <typename T, int P>
+__global__ void __launch_bounds__(TPB) fwd2d_kernel(const T *__restrict__ B, long long S, int nx,
+                                                    const double *__restrict__ sig, long long plane, long long n_first,
+                                                    int stride, int dim, T *dst, long long dst_stride,
+                                                    const T *__restrict__ G, T *Vout)
+{
+    const int c = blockIdx.y;
+    const long long n = n_first + (long long)c * stride;
+    const T *b = B + (long long)c * S;
+    const double *sx = sig + n * S, *sy = sig + plane + n * S;
+    constexpr int q = DTaps<P>::q;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        int i, jr;
+        split_xy(id, nx, i, jr);
+        if (dim != 2) jr = 0;
+        double dxv = 0.0, dyv = 0.0;
+#pragma unroll
+        for (int t = -q; t <= q; ++t) {
+            int ii = i + t;
+            ii += ii < 0 ? nx : 0;
+            ii -= ii >= nx ? nx : 0;
+            dxv += DTaps<P>::t[t + q] * double(b[(long long)jr * nx + ii]);
+            if (dim == 2) {
+                int jj = jr + t;
+                jj += jj < 0 ? nx : 0;
+                jj -= jj >= nx ? nx : 0;
+                dyv += DTaps<P>::t[t + q] * double(b[(long long)jj * nx + i]);
+            }
+        }
+        double y = double(b[id]) + sx[id] * dxv;
+        if (dim == 2) y += sy[id] * dyv;
+        T v = T(y);
+        if (G) v += G[(n + 1) * S + id];
+        dst[c * dst_stride + id] = v;
+        if (Vout) Vout[(n + 1) * S + id] = v;
+    }
+}
+
 __global__ void g2_count(const Gs2 *gs, int nsys, unsigned long long *counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -509,6 +550,23 @@ hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, const T *V, T *W, lon
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fwd2d(int p, dim3 grid, hipStream_t st, const T *B, long long S, int nx, const double *sig,
+                        long long plane, long long n_first, int stride, int dim, T *dst, long long dst_stride,
+                        const T *G, T *Vout)
+{
+#define FW(PP) hipLaunchKernelGGL((fwd2d_kernel<T, PP>), grid, dim3(TPB), 0, st, B, S, nx, sig, plane, n_first, \
+                                  stride, dim, dst, dst_stride, G, Vout)
+    switch (p) {
+    case 1: FW(1); break;
+    case 3: FW(3); break;
+    case 5: FW(5); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef FW
+    return hipGetLastError();
+}
+
 // One batch of chains [c0, c0+nch) of a sweep, all in the same level.
 template <typename T>
 hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0, int nch, hipStream_t st)
@@ -566,6 +624,13 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                 e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bb, S, (const double *)ws_at(P, L.disp),
                                            plane, nx, n_first0 + k, a.stride_chain, nullptr, nullptr);
                 if (e != hipSuccess) return e;
+            }
+            if (a.fwd) {                         // explicit correction, no linear solve
+                e = launch_fwd2d<T>(P.d.p, grid, st, rhs, S, nx, (const double *)ws_at(P, L.sigma), plane,
+                                    n_first0 + k, a.stride_chain, P.d.dim, bufs[cur ^ 1], S, (const T *)a.G, vo);
+                if (e != hipSuccess) return e;
+                cur ^= 1;
+                continue;
             }
             T *V = (T *)ws_at(P, P.g2v);
             T *W = (T *)ws_at(P, P.g2w);

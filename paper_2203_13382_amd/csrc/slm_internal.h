@@ -85,6 +85,7 @@ struct ChainArgs {
     int nsmall;              // |displacement| bound < nx - p - 1 (cheap wrap)
     int adj;                 // 1: adjoint system in reverse time (transposed steps)
     int Nl;                  // level steps; step n of the adjoint uses forward step Nl-1-n
+    int fwd;                 // coarse level with the explicit forward-Euler operator (eq. Fp_def)
 };
 
 // launchers (slm_chain1d.hip / slm_setup.hip / slm_misc.hip)

@@ -447,6 +447,55 @@ struct Gmres1D {
     }
 };
 
+// Explicit forward-Euler correction of eq. (Fp_def) in place:
+// x <- x + sigma .* (D_{p+1} x), with the same halo exchange through the
+// padded LDS buffer as the GMRES stencil.  Ends with a barrier, so the
+// buffer (aliased with the slice) may be rewritten afterwards.
+template <typename T, int P, int EPT, bool FULL>
+__device__ __forceinline__ void fwd_euler_apply(T (&x)[EPT], const double *sgp, T *xp, int nx)
+{
+    const int tid = threadIdx.x, i0 = tid * EPT;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+        if (FULL || i0 + e < nx) xp[pidx<EPT>(i0 + e)] = x[e];
+    __syncthreads();
+    constexpr int q = DTaps<P>::q;
+    T win[EPT + 2 * q];
+#pragma unroll
+    for (int t = 0; t < q; ++t) {
+        int il = i0 - q + t;
+        il += il < 0 ? nx : 0;
+        int ir = i0 + EPT + t;
+        ir -= ir >= nx ? nx : 0;
+        win[t] = (FULL || i0 < nx) ? xp[pidx<EPT>(il)] : T(0);
+        win[EPT + q + t] = (FULL || i0 < nx) ? xp[pidx<EPT>(ir)] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) win[q + e] = x[e];
+    if (!FULL && i0 + EPT > nx) {
+#pragma unroll
+        for (int e = 0; e < EPT + q; ++e) {
+            const int i = i0 + e;
+            if (i >= nx && i - nx < nx) win[q + e] = xp[pidx<EPT>(i - nx)];
+        }
+    }
+    T y[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        if (FULL || i0 + e < nx) {
+            double dv = 0.0;
+#pragma unroll
+            for (int t = 0; t <= 2 * q; ++t) dv += DTaps<P>::t[t] * double(win[e + t]);
+            y[e] = T(double(x[e]) + sgp[pidx<EPT>(i0 + e)] * dv);
+        } else {
+            y[e] = T(0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) x[e] = y[e];
+}
+
 // LDS layout of the coarse kernel: slice (natural order) aliased with the
 // padded exchange buffer (the slice is dead while GMRES runs) | sigma
 // (padded) | reduction scratch | Givens scalars.
@@ -464,7 +513,9 @@ __host__ __device__ inline size_t coarse_lds_parts(int nx, size_t *o_sg, size_t 
     return o + sizeof(GmresScalars);
 }
 
-template <typename T, int P, int EPT, bool FULL = false>
+// FWD: the explicit forward-Euler correction replaces the GMRES solve (a
+// variant of its own, so the GMRES kernel's register allocation is untouched).
+template <typename T, int P, int EPT, bool FULL = false, bool FWD = false>
 __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned char *smem)
 {
     const int tid = threadIdx.x, nx = a.nx;
@@ -510,8 +561,12 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
             val[e] = (FULL || i < nx) ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
         }
         __syncthreads();                         // every read of the slice is done, sigma staged
-        niter += gm.solve(val, sgp, xp, red, rb, gs, a.kmax, a.rtol, nx);
-        ++nsolve;
+        if constexpr (FWD) {
+            fwd_euler_apply<T, P, EPT, FULL>(val, sgp, xp, nx);
+        } else {
+            niter += gm.solve(val, sgp, xp, red, rb, gs, a.kmax, a.rtol, nx);
+            ++nsolve;
+        }
         const bool wv = Vout && (k + 1 < a.nsteps || a.write_last);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -551,11 +606,11 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
     }
 }
 
-template <typename T, int P, int EPT, bool FULL>
+template <typename T, int P, int EPT, bool FULL, bool FWD = false>
 __global__ void __launch_bounds__(COARSE_MAXB) coarse1d(ChainArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    coarse_chain<T, P, EPT, FULL>(a, blockIdx.x, smem);
+    coarse_chain<T, P, EPT, FULL, FWD>(a, blockIdx.x, smem);
 }
 
 // Prefetch depth of the displacement ring: about 64 bytes per lane in

@@ -69,6 +69,7 @@ ChainArgs base_args(const slm_plan &P, int level)
     a.nsmall = level == 0 && disp_bound(P) + P.d.p + 8 < P.d.nx ? 1 : 0;
     a.adj = P.adj_mode;
     a.Nl = P.lv[level].N;
+    a.fwd = level > 0 && P.d.coarse_op == SLM_COARSE_FWD_EULER ? 1 : 0;
     return a;
 }
 
@@ -309,10 +310,14 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
     if (d->max_iter < 1) return fail(nullptr, SLM_EINVAL, "max_iter >= 1 required");
     if (d->precision != SLM_FP64 && d->precision != SLM_FP32_BULK) return fail(nullptr, SLM_EINVAL, "bad precision");
     if (d->adjoint != 0 && d->adjoint != 1) return fail(nullptr, SLM_EINVAL, "adjoint must be 0 or 1");
-    if (d->coarse_op != SLM_COARSE_MODIFIED && d->coarse_op != SLM_COARSE_REDISC)
-        return fail(nullptr, SLM_EUNSUPPORTED, "coarse_op must be SLM_COARSE_MODIFIED or SLM_COARSE_REDISC");
+    if (d->coarse_op != SLM_COARSE_MODIFIED && d->coarse_op != SLM_COARSE_REDISC &&
+        d->coarse_op != SLM_COARSE_FWD_EULER)
+        return fail(nullptr, SLM_EUNSUPPORTED,
+                    "coarse_op must be SLM_COARSE_MODIFIED, SLM_COARSE_REDISC or SLM_COARSE_FWD_EULER");
     if (d->coarse_op == SLM_COARSE_REDISC && (d->precision != SLM_FP64 || d->adjoint))
         return fail(nullptr, SLM_EUNSUPPORTED, "the rediscretized coarse operator needs SLM_FP64 and no adjoint");
+    if (d->coarse_op == SLM_COARSE_FWD_EULER && (d->precision != SLM_FP64 || d->adjoint))
+        return fail(nullptr, SLM_EUNSUPPORTED, "the forward-Euler coarse operator needs SLM_FP64 and no adjoint");
     if (d->adjoint && (d->precision != SLM_FP64 || d->p % 2 == 0))
         return fail(nullptr, SLM_EUNSUPPORTED, "the adjoint needs SLM_FP64 and odd p");
     if (d->adjoint && d->n_alpha + (d->dim == 2 ? d->n_beta : 0) > 16)
@@ -345,9 +350,9 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
         P->L = l + 2;
     }
     P->lv[P->L - 1].m = 0;
-    if (P->L > 1 && (d->p % 2) == 0 && d->coarse_op == SLM_COARSE_MODIFIED) {
+    if (P->L > 1 && (d->p % 2) == 0 && d->coarse_op != SLM_COARSE_REDISC) {
         delete P;
-        return fail(nullptr, SLM_EUNSUPPORTED, "MGRIT with the modified coarse operator needs odd p");
+        return fail(nullptr, SLM_EUNSUPPORTED, "MGRIT with the modified or forward-Euler coarse operator needs odd p");
     }
     if (d->adjoint && P->L < 2) {
         delete P;

@@ -5,8 +5,9 @@ paper.
 For constant speed, every fine semi-Lagrangian step is the same circulant
 matrix, so it acts on the Fourier mode exp(i w k) by a factor lambda(w).  The
 coarse operator acts by mu(w): the rediscretized step S(m dt) of Sec. 2.3,
-or the backward-Euler coarse operator of eq. (Bp_def),
-[I - phi D_{p+1}]^{-1} S(m dt), with the constant phi of eq. (varphi_p_def)
+the backward-Euler coarse operator of eq. (Bp_def),
+[I - phi D_{p+1}]^{-1} S(m dt), or the forward-Euler one of eq. (Fp_def),
+[I + phi D_{p+1}] S(m dt), with the constant phi of eq. (varphi_p_def)
 and D_{p+1} the second-order central difference (delta^2)^{(p+1)/2}.  The
 estimate of eq. (rho_MGRIT_asym) is
     rho(c) = max_w |lambda|^m |lambda^m - mu| / (1 - |mu|)
@@ -84,12 +85,16 @@ def phi_two_level(p: int, c: float, m: int) -> float:
 
 
 def coarse_symbol(p: int, c: float, m: int, w: np.ndarray, coarse: str = "modified") -> np.ndarray:
-    """mu(w): rediscretized S(m dt), or [I - phi D_{p+1}]^{-1} S(m dt)."""
+    """mu(w): rediscretized S(m dt), the backward-Euler operator
+    [I - phi D_{p+1}]^{-1} S(m dt) ('modified'), or the forward-Euler
+    operator [I + phi D_{p+1}] S(m dt) ('fwd_euler')."""
     mu = sl_symbol(p, m * c, w)
     if coarse == "redisc":
         return mu
+    if coarse == "fwd_euler":                  # eq. (Fp_def)
+        return mu * (1.0 + phi_two_level(p, c, m) * dp1_symbol(p, w))
     if coarse != "modified":
-        raise ValueError("coarse must be 'modified' or 'redisc'")
+        raise ValueError("coarse must be 'modified', 'fwd_euler' or 'redisc'")
     return mu / (1.0 - phi_two_level(p, c, m) * dp1_symbol(p, w))
 
 

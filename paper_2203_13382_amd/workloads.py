@@ -42,7 +42,7 @@ class Solver:
     max_levels: int = 64
     coarsest_max_points: int = 2
     relax: str = "FCF"            # "F" or "FCF"
-    coarse_op: str = "modified"   # "modified", "ideal", "redisc"
+    coarse_op: str = "modified"   # "modified", "ideal", "redisc", "fwd_euler"
     gmres_kmax: int = 10
     gmres_rtol: float = 1e-2      # 0 => exactly gmres_kmax iterations
     tol: float = 1e-10

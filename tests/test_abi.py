@@ -169,3 +169,20 @@ def test_redisc_descriptor_validation():
     d, k = N.make_desc(dataclasses.replace(pr, p=2), W.Solver(m=[4], coarse_op="redisc"), "fp64")
     assert L.slm_plan_create(C.byref(d), C.byref(h)) == 0
     L.slm_plan_destroy(h)
+
+
+def test_fwd_euler_descriptor_validation():
+    """The forward-Euler coarse operator (eq. Fp_def) is FP64-only, has no
+    adjoint and, like the backward-Euler one, needs odd p."""
+    import dataclasses
+    L = N.lib()
+    pr = W.Problem(1, 64, 32, 0.05, 3, 3, W.alpha_cfg12())
+    h = C.c_void_p()
+    sv = W.Solver(m=[4], coarse_op="fwd_euler")
+    for prob, prec, adj, rc in [(pr, "fp32", False, -2), (pr, "fp64", True, -2),
+                                (dataclasses.replace(pr, p=2), "fp64", False, -2), (pr, "fp64", False, 0)]:
+        d, k = N.make_desc(prob, sv, prec, adj)
+        got = L.slm_plan_create(C.byref(d), C.byref(h))
+        assert got == rc, (prob.p, prec, adj, got)
+        if got == 0:
+            L.slm_plan_destroy(h)

@@ -56,10 +56,10 @@ def test_phi_matches_oracle_sigma(oracle, p, c, m):
 @pytest.mark.parametrize("p", [1, 3])
 @pytest.mark.parametrize("c,m", [(0.85, 4), (0.6, 8), (1.3, 2)])
 def test_coarse_symbols_match_oracle(oracle, p, c, m):
-    """mu(w) of both coarse operators against the oracle's level-1 step with
+    """mu(w) of the three coarse operators against the oracle's level-1 step with
     an exact linear solve (nx = 8, Krylov space of dimension 8)."""
     nx = 8
-    for coarse in ("modified", "redisc"):
+    for coarse in ("modified", "redisc", "fwd_euler"):
         pr = W.Problem(1, nx, 4 * m, c * 2.0 / nx, p, p, [W.term(1.0)], [])
         sv = W.Solver(m=[m], max_levels=2, gmres_kmax=10, gmres_rtol=0.0, coarse_op=coarse)
         ctx = oracle.Context(pr, sv)
@@ -84,7 +84,24 @@ def test_paper_statements():
             assert max(r) < 1.0, (p, m, max(r))
 
 
+def test_forward_euler_statements():
+    """Sec. 3.2, case 1: for constant speed the forward-Euler correction
+    I + phi D_{p+1} is stable for small m (|1 + phi d(w)| <= 1, and the
+    estimate is below 1 for every CFL number) and unstable for larger m
+    (norm above 1, the estimate above 1 for some CFL numbers)."""
+    w = F.omegas()
+    cs = np.linspace(0.05, 4.0, 80)
+    for p in (1, 3):
+        for m in (2, 4):
+            assert max(np.abs(1 + F.phi_two_level(p, c, m) * F.dp1_symbol(p, w)).max() for c in cs) <= 1 + 1e-12
+            assert max(F.rho(p, c, m, "fwd_euler") for c in cs) < 1
+        for m in (8, 16):
+            assert max(np.abs(1 + F.phi_two_level(p, c, m) * F.dp1_symbol(p, w)).max() for c in cs) > 1.5
+            assert max(F.rho(p, c, m, "fwd_euler") for c in cs) > 1
+
+
 @pytest.mark.parametrize("p,c,m,coarse", [(1, 0.8, 4, "modified"), (3, 0.8, 4, "modified"),
+                                          (1, 0.8, 2, "fwd_euler"),
                                           (1, 0.9, 4, "redisc"), (1, 0.62, 2, "redisc")])
 def test_estimate_matches_measured_factor(oracle, p, c, m, coarse):
     """Two-level FCF MGRIT with 10 GMRES iterations (rtol 0) on alpha = 1:

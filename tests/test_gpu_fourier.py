@@ -2,7 +2,9 @@
 speed (alpha = 1, nx = 128, nt = 2^14, 10 GMRES iterations with rtol 0, as
 for the measured points of Figs. 2 and 3) against the Fourier estimate of
 eq. (rho_MGRIT_asym): the factor of the last cycle lies within 20% below
-and 5% above the estimate, and above 1 where the estimate is."""
+and 5% above the estimate, and above 1 where the estimate is.  Even p with
+the rediscretized operator (MGRIT the paper finds non-robust, Sec. 3.2)
+diverges, as the estimate predicts."""
 import numpy as np
 import pytest
 
@@ -21,7 +23,7 @@ def torch():
 
 @pytest.mark.parametrize("p,c,m,coarse", [(1, 0.8, 4, "modified"), (3, 0.8, 4, "modified"),
                                           (3, 0.6, 8, "modified"), (1, 0.9, 4, "redisc"),
-                                          (1, 0.62, 2, "redisc")])
+                                          (1, 0.62, 2, "redisc"), (2, 0.8, 4, "redisc")])
 def test_measured_factor_matches_estimate(torch, p, c, m, coarse):
     from paper_2203_13382_amd import Plan
     nx, nt = 128, 2 ** 14
@@ -37,6 +39,11 @@ def test_measured_factor_matches_estimate(torch, p, c, m, coarse):
     est = F.rho(p, c, m, coarse)
     print(f"p={p} c={c} m={m} {coarse}: measured {fac:.4f}, estimate {est:.4f}, "
           f"{st['iterations']} cycles ({st['status']})", flush=True)
+    if est > 2:
+        # far outside the range where the estimate is quantitative (even p:
+        # |mu| close to 1 at some frequency); the run must still diverge
+        assert fac > 1 and st["status"] != "converged"
+        return
     assert 0.8 * est <= fac <= 1.05 * est, (fac, est)
     if est > 1:
         assert fac > 1
