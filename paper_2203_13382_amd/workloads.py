@@ -156,3 +156,31 @@ def adjoint_config(seed: int = 5, **over):
     sv = Solver(m=[4], coarsest_max_points=16, relax="FCF", gmres_kmax=10, gmres_rtol=1e-2,
                 tol=over.get("tol", 1e-10), tol_mode="rel", max_iter=100)
     return pr, sv, theta, theta_true
+
+
+def paper_problem(dim: int, field: str, p: int, nx: int, nt: int) -> Problem:
+    """The paper's test problems (Sec. 5 for 1D, Sec. 6 for 2D), dt = 0.85 h,
+    r = p.  1D fields: 'a1' alpha = 1, 'a2' alpha = cos(2 pi t), 'a4' alpha =
+    cos(2 pi t) cos(2 pi x); 2D: 'const' (alpha, beta) = (1, 1) and 'var', the
+    time-dependent field of eq. (alpha-var_2D)."""
+    dt = 0.85 * 2.0 / nx
+    if dim == 2:
+        kt = 2.0 / 3.4
+        fields = {"const": ([term(1.0)], [term(1.0)]),
+                  "var": ([term(0.5, kt=kt), term(-0.5, ky=2.0, kt=kt)],
+                          [term(-0.5, kt=kt), term(-0.5, kx=2.0, kt=kt)])}
+        a, b = fields[field]
+        return Problem(2, nx, nt, dt, p, p, a, b)
+    alpha = {"a1": [term(1.0)], "a2": [term(1.0, kt=2.0)], "a4": [term(1.0, kx=2.0, kt=2.0)]}[field]
+    return Problem(1, nx, nt, dt, p, p, alpha, [])
+
+
+def paper_initial_condition(dim: int, nx: int):
+    """u0 = sin^4(pi x) in 1D; sin^2(pi/2 (x-1)) sin^2(pi/2 (y-1)) in 2D."""
+    import numpy as np
+    x = -1.0 + np.arange(nx) * (2.0 / nx)
+    if dim == 1:
+        return np.sin(np.pi * x) ** 4
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    return (np.sin(np.pi / 2 * (X - 1)) ** 2 * np.sin(np.pi / 2 * (Y - 1)) ** 2).reshape(-1)
+

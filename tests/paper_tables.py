@@ -3,9 +3,6 @@ from tests/golden/paper_iterations.txt and the problem and solver each cell
 describes.  Used by the oracle's pins and by the GPU reproduction."""
 import os
 
-import numpy as np
-
-from paper_2203_13382_amd import inputs as I
 from paper_2203_13382_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_iterations.txt")
@@ -17,45 +14,32 @@ def rows():
         if not line.strip() or line.startswith("#"):
             continue
         f = line.split()
-        out.append(dict(table=f[0], field=f[1], p=int(f[2]), nx=int(f[3]), nt=int(f[4]), m=int(f[5]),
+        m = [int(x) for x in f[5].split(",")] if "," in f[5] else int(f[5])
+        out.append(dict(table=f[0], field=f[1], p=int(f[2]), nx=int(f[3]), nt=int(f[4]), m=m,
                         iters=int(f[6]), redisc=int(f[7]) if len(f) > 7 else None))
     return out
 
 
 def row_id(r, prefix=""):
-    return f"{prefix or r['table']}-{r['field']}-p{r['p']}-nx{r['nx']}-m{r['m']}"
+    m = "-".join(str(x) for x in r["m"]) if isinstance(r["m"], list) else r["m"]
+    return f"{prefix or r['table']}-{r['field']}-p{r['p']}-nx{r['nx']}-m{m}"
 
 
 def problem(row):
-    """Section 5 (1D: eq. (ad) with the three wave speeds, u0 = sin^4(pi x))
-    and Section 6 (2D: eq. (ad_2D), constant (1, 1) or the time-dependent
-    field, u0 = sin^2(pi/2 (x-1)) sin^2(pi/2 (y-1))); dt = 0.85 h, r = p."""
-    nx, nt, p = row["nx"], row["nt"], row["p"]
-    dt = 0.85 * 2.0 / nx
-    if row["table"] == "T3":
-        kt = 2.0 / 3.4
-        fields = {"const": ([W.term(1.0)], [W.term(1.0)]),
-                  "var": ([W.term(0.5, kt=kt), W.term(-0.5, ky=2.0, kt=kt)],
-                          [W.term(-0.5, kt=kt), W.term(-0.5, kx=2.0, kt=kt)])}
-        a, b = fields[row["field"]]
-        pr = W.Problem(2, nx, nt, dt, p, p, a, b)
-        x = I.mesh(nx)
-        X, Y = np.meshgrid(x, x, indexing="xy")
-        u0 = (np.sin(np.pi / 2 * (X - 1)) ** 2 * np.sin(np.pi / 2 * (Y - 1)) ** 2).reshape(-1)
-    else:
-        alpha = {"a1": [W.term(1.0)], "a2": [W.term(1.0, kt=2.0)],
-                 "a4": [W.term(1.0, kx=2.0, kt=2.0)]}[row["field"]]
-        pr = W.Problem(1, nx, nt, dt, p, p, alpha, [])
-        u0 = np.sin(np.pi * I.mesh(nx)) ** 4
-    return pr, u0
+    """The cell's problem and initial condition (workloads.paper_problem)."""
+    dim = 2 if row["table"] == "T3" else 1
+    pr = W.paper_problem(dim, row["field"], row["p"], row["nx"], row["nt"])
+    return pr, W.paper_initial_condition(dim, row["nx"])
 
 
 def solver(row, coarse_op="modified"):
     """Table 1: two levels, coarse operator of eq. (Psi_Bp_def2) with exactly
-    10 GMRES iterations; Tables 2 and 3: V-cycles down to 2 points, GMRES to
-    relative residual 1e-2 or 10 iterations; m on every level; stop at a
-    relative residual of 1e-10."""
+    10 GMRES iterations; Tables 2 and 3 and the Sec. 5 runs: V-cycles down to
+    2 points, GMRES to relative residual 1e-2 or 10 iterations; m on every
+    level (Sec. 5: 16 on the first, 4 below); stop at a relative residual of
+    1e-10."""
     if row["table"] == "T1":
         return W.Solver(m=[row["m"]], max_levels=2, gmres_kmax=10, gmres_rtol=0.0, max_iter=300)
-    return W.Solver(m=[row["m"]], coarsest_max_points=2, gmres_kmax=10, gmres_rtol=1e-2,
+    m = row["m"] if isinstance(row["m"], list) else [row["m"]]
+    return W.Solver(m=m, coarsest_max_points=2, gmres_kmax=10, gmres_rtol=1e-2,
                     max_iter=300, coarse_op=coarse_op)
