@@ -101,17 +101,24 @@ __device__ __forceinline__ void chain_start(const ChainArgs &a, int j, T *sl, T 
     const T *Cin = static_cast<const T *>(a.Cin);
     T *Vout = static_cast<T *>(a.Vout);
     T *Cout = static_cast<T *>(a.Cout);
+    // all loads first, then the stores (a store to Vout or Cout could alias
+    // Cin, so interleaving them would serialise the loads)
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) val[e] = T(0);
+    if (Cin) {
+        const T *c = Cin + (long long)j * a.cin_stride;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+            if (tid + e * B < nx) val[e] = c[tid + e * B];
+    }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int i = tid + e * B;
-        T s = T(0);
         if (i < nx) {
-            if (Cin) s = Cin[(long long)j * a.cin_stride + i];
-            sl[i] = s;
-            if (Vout && a.write_start) Vout[n_first * a.S + i] = s;
-            if (Cout && j == 0 && a.cout_shift) Cout[i] = s;
+            sl[i] = val[e];
+            if (Vout && a.write_start) Vout[n_first * a.S + i] = val[e];
+            if (Cout && j == 0 && a.cout_shift) Cout[i] = val[e];
         }
-        val[e] = s;
     }
 }
 
@@ -134,11 +141,19 @@ __device__ __forceinline__ void chain_finish(const ChainArgs &a, int j, const T 
         const T *Cref = static_cast<const T *>(a.Cref);
         T *R = static_cast<T *>(a.R);
         double acc[1] = {0.0};
+        T cv[EPT];                               // Cref in one batch of loads
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) cv[e] = T(0);
+        if (Cref) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if (tid + e * B < nx) cv[e] = Cref[(long long)(j + 1) * S + tid + e * B];
+        }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = tid + e * B;
             if (i < nx) {
-                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
+                const T r = Cref ? T(val[e] - cv[e]) : val[e];
                 R[(long long)(j + 1) * S + i] = r;
                 acc[0] += double(r) * double(r);
             }
@@ -552,13 +567,24 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
     int rb = 0;
     Gmres1D<T, P, EPT, FULL> gm;
     unsigned long long nsolve = 0, niter = 0;
+    // Displacements and sigma of the next step are loaded right after the
+    // current step's solve, next to its G(n+1) loads: the step pays one
+    // memory latency instead of two, and the registers are only live while
+    // the Krylov basis is not.
+    double dnx[EPT], snx[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int i = i0 + e;
+        dnx[e] = (FULL || i < nx) && a.nsteps > 0 ? disp[n_first * S + i] : 0.0;
+        snx[e] = (FULL || i < nx) && a.nsteps > 0 ? a.sigma[n_first * S + i] : 0.0;
+    }
     for (int k = 0; k < a.nsteps; ++k) {
         const long long n = n_first + k;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = i0 + e;
-            if (FULL || i < nx) sgp[pidx<EPT>(i)] = a.sigma[n * S + i];
-            val[e] = (FULL || i < nx) ? interp1<P, T, double>(sl, i, disp[n * S + i], nx, 0) : T(0);
+            if (FULL || i < nx) sgp[pidx<EPT>(i)] = snx[e];
+            val[e] = (FULL || i < nx) ? interp1<P, T, double>(sl, i, dnx[e], nx, 0) : T(0);
         }
         __syncthreads();                         // every read of the slice is done, sigma staged
         if constexpr (FWD) {
@@ -567,12 +593,30 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
             niter += gm.solve(val, sgp, xp, red, rb, gs, a.kmax, a.rtol, nx);
             ++nsolve;
         }
+        const long long nn = k + 1 < a.nsteps ? n + 1 : n;    // the last step re-reads its own (cached) rows
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+            const int i = i0 + e;
+            dnx[e] = (FULL || i < nx) ? disp[nn * S + i] : 0.0;
+            snx[e] = (FULL || i < nx) ? a.sigma[nn * S + i] : 0.0;
+        }
+        // G(n+1) in one batch of loads (a per-node test of G would issue and
+        // wait for them one at a time)
+        T gv[EPT];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) gv[e] = T(0);
+        if (G) {
+            const T *gn = G + (n + 1) * S;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if (FULL || i0 + e < nx) gv[e] = gn[i0 + e];
+        }
         const bool wv = Vout && (k + 1 < a.nsteps || a.write_last);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = i0 + e;
             if (FULL || i < nx) {
-                if (G) val[e] += G[(n + 1) * S + i];
+                if (G) val[e] += gv[e];
                 sl[i] = val[e];
                 if (wv) Vout[(n + 1) * S + i] = val[e];
             }
@@ -588,11 +632,19 @@ __device__ __forceinline__ void coarse_chain(const ChainArgs &a, int j, unsigned
         const T *Cref = static_cast<const T *>(a.Cref);
         T *R = static_cast<T *>(a.R);
         double acc[1] = {0.0};
+        T cv[EPT];                               // Cref in one batch of loads
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) cv[e] = T(0);
+        if (Cref) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+                if (FULL || i0 + e < nx) cv[e] = Cref[(long long)(j + 1) * S + i0 + e];
+        }
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
             const int i = i0 + e;
             if (FULL || i < nx) {
-                const T r = Cref ? T(val[e] - Cref[(long long)(j + 1) * S + i]) : val[e];
+                const T r = Cref ? T(val[e] - cv[e]) : val[e];
                 R[(long long)(j + 1) * S + i] = r;
                 acc[0] += double(r) * double(r);
             }
