@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(TPB) g2_sum(const double *__restrict__ part, i
         for (int q = 0; q <= SLM_KMAX; ++q)
             if (q < nv) v[q] += pp[q];
     }
-    block_sum<SLM_KMAX + 1>(v, red, 0);
+    block_sum_rs<SLM_KMAX + 1>(v, red, 0);
     if (threadIdx.x < nv) out[(long long)c * NPART + threadIdx.x] = v[threadIdx.x];
 }
 
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__r
         for (int k = 0; k <= SLM_KMAX; ++k)
             if (k <= j) h[k] += double(Vc[(long long)k * S + id]) * double(w);
     }
-    block_sum<SLM_KMAX + 1>(h, red, 0);
+    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
     if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
@@ -344,7 +344,7 @@ __global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__r
             h[0] += double(w) * double(w);
         }
     }
-    block_sum<SLM_KMAX + 1>(h, red, 0);
+    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
     const int nv = dots ? j + 1 : 1;
     if (threadIdx.x < nv) part_out[((long long)c * nb + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }

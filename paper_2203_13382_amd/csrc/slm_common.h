@@ -274,6 +274,26 @@ __device__ __forceinline__ void wave_sums_to_lds(const double (&v)[NV], double *
     }
 }
 
+// block_sum with the reduce-scatter wave stage (fewer instructions for many
+// values; used by the batched 2D kernels, whose blocks each reduce up to
+// SLM_KMAX+1 partial inner products).  Every thread receives the totals,
+// summed over the waves in a fixed order.
+template <int NV>
+__device__ __forceinline__ void block_sum_rs(double (&v)[NV], double *red, int buf)
+{
+    const int wid = threadIdx.x / SLM_WAVE;
+    const int nw = blockDim.x / SLM_WAVE;
+    double *r = red + buf * (SLM_MAXB / SLM_WAVE) * 16;
+    wave_sums_to_lds<NV>(v, r + wid * 16);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += r[w * 16 + i];
+        v[i] = s;
+    }
+}
+
 // block_sum variant whose totals come back as wave-uniform values (scalar
 // registers): each wave reduce-scatters its partial sums into LDS, then lane
 // l < NV adds up value l over the waves in a fixed order and each total is
