@@ -552,7 +552,7 @@ hipError_t launch_grad(const slm_plan &P, int nch, const double *U, long long u_
 {
     const long long S = P.S;
     const double *disp = (const double *)ws_at(P, P.lv[0].disp);
-    const dim3 grid(nblk(S), nch);
+    const dim3 grid(P.nb2, nch);                 // gacc holds P.nb2 slots per interval
     const double h = 2.0 / P.d.nx;
     const int c0 = (int)(n_first / stride);
 #define GK(PP, RR, DD) hipLaunchKernelGGL((grad_kernel<PP, RR, DD>), grid, dim3(TPB), 0, st, U, u_stride, lam, \
@@ -571,7 +571,7 @@ hipError_t launch_grad(const slm_plan &P, int nch, const double *U, long long u_
 hipError_t launch_grad_reduce(const slm_plan &P, int nchains, double *out, hipStream_t st)
 {
     hipLaunchKernelGGL(grad_reduce, dim3(1), dim3(TPB), 0, st, (const double *)ws_at(P, P.gacc),
-                       (long long)nchains * nblk(P.S), P.nq, out);
+                       (long long)nchains * P.nb2, P.nq, out);
     return hipGetLastError();
 }
 

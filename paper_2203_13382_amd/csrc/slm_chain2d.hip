@@ -477,9 +477,13 @@ __global__ void g2_count(const Gs2 *gs, int nsys, unsigned long long *counter)
 }
 
 // ------------------------------------------------------------ host side
+// Blocks per system of the batched kernels: about four nodes per thread, so
+// the per-block partial sums (up to 11 values) are amortised over several
+// nodes; at most 1024.  Every per-block buffer (part2, the GMRES partials,
+// the adjoint's gradient slots) is sized and indexed with this count.
 int nblocks(long long S)
 {
-    long long b = (S + TPB - 1) / TPB;
+    long long b = (S + 4 * TPB - 1) / (4 * TPB);
     return (int)(b < 1024 ? b : 1024);
 }
 
