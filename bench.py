@@ -400,7 +400,7 @@ def updates_of(N, m, iterations, fcf, L):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU time-slab sharding "
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU time-slab sharding "
                                    "is a design note only (--gpus must be 1)"}))
         sys.exit(2)
     import torch

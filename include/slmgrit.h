@@ -64,7 +64,7 @@ enum {
     SLM_DIVERGED = 2,          /* residual norm not finite (no growth test) */
     SLM_STAGNATED = 3,         /* FP32 bulk: ratio > 0.95 for 3 cycles */
     SLM_EINVAL = -1,           /* invalid argument or descriptor */
-    SLM_EUNSUPPORTED = -2,     /* valid but not supported by this build */
+    SLM_EUNSUPPORTED = -2,     /* valid but not supported by this library */
     SLM_EWORKSPACE = -3,       /* workspace missing or too small */
     SLM_EHIP = -4,             /* a HIP runtime call failed */
     SLM_ENOTSETUP = -5         /* slm_plan_setup() has not run */
