@@ -144,6 +144,16 @@ int slm_plan_setup(slm_plan *plan, void *d_ws, size_t bytes, void *stream);
 int slm_level_arrays(const slm_plan *plan, int level, const void **d_disp,
                      int *disp_is_f32, const void **d_sigma);
 
+/* Launch shape of level l's relaxation step (the SL step of Sec. 2.1 /
+ * 4.1 on level 0, eq. (BEOper_2D) on coarse levels) for a call over
+ * `nchains` intervals or slices, for tests and profiling: *tiled = 1 when
+ * the 2D level-0 step stages each tile's source window in LDS (0: the plain
+ * gather kernel; always 0 in 1D and on coarse levels); *blocks_per_system =
+ * workgroups per slice of the batched 2D kernels, whose per-block partial
+ * sums are reduced in a fixed order (1 in 1D).  Either pointer may be NULL.
+ * Host only. */
+int slm_launch_info(const slm_plan *plan, int level, int nchains, int *tiled, int *blocks_per_system);
+
 /* out[k] = Phi_l(n0+k) in[k] for k < count: one level-l time step applied to
  * `count` independent slices (T, [count][S]); n0+count <= N_l.  Level 0 is
  * the SL step S_{p,r}; level l >= 1 is eq. (Phi_multilevel) / (BEOper_2D)
@@ -167,9 +177,27 @@ int slm_relax(slm_plan *plan, int level, int mode, const void *d_g,
               const void *d_c_in, void *d_c_out, void *d_res, void *d_v,
               double *h_norm, void *stream);
 
-/* Sequential stepping u_{n+1} = Phi_0 u_n from d_u0 (T, [S]).  store_all:
- * d_u receives [(nt+1)][S]; otherwise only u_{nt} ([S]). */
+/* Sequential time stepping: u_{n+1} = S_{p,r}(t_n) u_n for n = 0..nt-1
+ * from d_u0 (T, [S]), i.e. forward substitution through the one-step
+ * system (eq. one-step) with the fine SL step of Sec. 2.1 (Sec. 4.1 in 2D);
+ * this is the serial time-stepping the paper compares MGRIT against
+ * (Sec. 5).  store_all: d_u receives [(nt+1)][S]; otherwise only u_{nt}
+ * ([S]).  Needs setup (the fine departure points); asynchronous. */
 int slm_step(slm_plan *plan, const void *d_u0, void *d_u, int store_all, void *stream);
+
+/* Seeded initial iterate of MGRIT (Sec. 2.2 starts from a random
+ * space-time guess, uniform in [0,1); the paper gives no generator).  Writes
+ * the C-points (fine time points n = j*m_0, j = 0..nt/m_0; every time point
+ * of a plan without coarsening) of d_u: the value at time point n and node k
+ * is the top 53 bits of the SplitMix64 output (Steele, Lea & Flood 2014) for
+ * the state seed XOR (n*S + k), as a fraction of 2^53, rounded to T.  It is
+ * a pure function of (seed, n, k), so any implementation reproduces it.
+ * layout SLM_ITERATE_FULL: d_u is [(nt+1)][S] (slm_solve's iterate);
+ * SLM_ITERATE_CPOINTS: d_u is [(nt/m_0)+1][S] (slm_solve_cpoints' iterate).
+ * Other entries are not touched.  Slice 0 is overwritten by u_0 in the
+ * solve.  Needs no setup; asynchronous on `stream`. */
+enum { SLM_ITERATE_FULL = 0, SLM_ITERATE_CPOINTS = 1 };
+int slm_seed_iterate(slm_plan *plan, uint64_t seed, void *d_u, int layout, void *stream);
 
 /* Linear MGRIT V-cycles (Sec. 2.2; linear variant of SM2) until the
  * tolerance test of the descriptor.  d_u ([(nt+1)][S], T) is in/out: on

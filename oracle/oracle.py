@@ -28,7 +28,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/libslmo.so``."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-fopenmp",
                                "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -111,6 +111,13 @@ def lib():
                                             C.c_double, _D, _D]
         L.slmo_weights_deps.argtypes = [C.c_int, C.c_double, _D]
         L.slmo_grad_theta.argtypes = [C.POINTER(CProblem), _D, _D, _D]
+        L.slmo_set_threads.argtypes = [C.c_int]
+        L.slmo_get_threads.restype = C.c_int
+        L.slmo_splitmix64.restype = C.c_uint64
+        L.slmo_splitmix64.argtypes = [C.c_uint64]
+        L.slmo_seeded_value.restype = C.c_double
+        L.slmo_seeded_value.argtypes = [C.c_uint64, C.c_uint64]
+        L.slmo_seeded_iterate.argtypes = [C.c_uint64, C.c_int, C.c_longlong, C.c_int, _D]
         _lib = L
     return _lib
 
@@ -336,6 +343,31 @@ def loss_and_gradient(pr, u0, u_obs):
     r = u[-1] - np.asarray(u_obs, dtype=np.float64).reshape(-1)
     lam = adjoint_seq(pr, r)
     return 0.5 * float(r @ r), lam[0].copy(), grad_theta(pr, u, lam)
+
+
+def set_threads(n):
+    """Threads the oracle may use (OpenMP); results do not depend on it."""
+    lib().slmo_set_threads(int(n))
+
+
+def get_threads():
+    return lib().slmo_get_threads()
+
+
+def splitmix64(state):
+    return lib().slmo_splitmix64(state & 0xFFFFFFFFFFFFFFFF)
+
+
+def seeded_value(seed, idx):
+    return lib().slmo_seeded_value(seed & 0xFFFFFFFFFFFFFFFF, idx & 0xFFFFFFFFFFFFFFFF)
+
+
+def seeded_iterate(seed, nt, S, m0):
+    """[(nt+1), S] array whose C-points (every m0-th time point) hold the
+    seeded initial iterate (slmo_seeded_iterate); the rest is zero."""
+    u = np.zeros((nt + 1, S))
+    lib().slmo_seeded_iterate(seed & 0xFFFFFFFFFFFFFFFF, nt, S, m0, _ptr(u))
+    return u
 
 
 def hierarchy(nt, sv):

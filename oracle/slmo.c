@@ -6,17 +6,44 @@
  * no blocking, no fusion, summations in index order.  See slmo.h for the
  * conventions.  Readings of passages where the paper is silent are marked
  * "Reading:".
+ *
+ * Threads (OpenMP, when compiled with it): the coarse intervals of a
+ * relaxation sweep, the time steps of the setup and the nodes of one
+ * interpolation are independent and may run on several threads.  Every sum
+ * is still taken in index order on one thread, so results do not depend on
+ * the thread count.
  */
 #include "slmo.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define SLMO_PI 3.14159265358979323846
 #define SLMO_MAXL 64
 
 static long long pmod(long long a, long long n) { long long r = a % n; return r < 0 ? r + n : r; }
+
+void slmo_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int slmo_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Problem data                                                              */
@@ -193,6 +220,7 @@ void slmo_depart_fine(const slmo_problem *pr, int n, double *xi, double *eta)
             slmo_erk_back(pr, -1.0 + i * h, 0.0, t_arr, pr->dt, &xi[i], &yd);
         }
     } else {
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < nx; j++)
             for (int i = 0; i < nx; i++)
                 slmo_erk_back(pr, -1.0 + i * h, -1.0 + j * h, t_arr, pr->dt,
@@ -219,6 +247,7 @@ void slmo_interp(int dim, int nx, int p, const double *xi, const double *eta,
         return;
     }
     long long S = (long long)nx * nx;
+#pragma omp parallel for schedule(static) private(wx, wy)
     for (long long k = 0; k < S; k++) {
         long long E, N; double eps, nu; int lx, rx, ly, ry;
         slmo_decompose(nx, xi[k], &E, &eps);
@@ -576,6 +605,37 @@ struct slmo_ctx {
     int adjoint;                            /* 1: reverse-time adjoint system */
 };
 
+/* Initial iterate of MGRIT.  Sec. 2.2 starts from a random space-time
+ * guess with entries uniform in [0,1) and gives no generator.  Reading: a
+ * counter-based draw, so that any implementation can reproduce it without
+ * sharing a random stream.  The value at fine time point n and node k is the
+ * SplitMix64 output (Steele, Lea & Flood, OOPSLA 2014) for the state
+ * seed XOR (n*S + k), keeping its top 53 bits as a fraction of 2^53.
+ * SplitMix64's output for a state x: z = x + 0x9e3779b97f4a7c15, then
+ * z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9, z = (z ^ (z >> 27)) *
+ * 0x94d049bb133111eb, result z ^ (z >> 31). */
+uint64_t slmo_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double slmo_seeded_value(uint64_t seed, uint64_t idx)
+{
+    return (double)(slmo_splitmix64(seed ^ idx) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* u is [(nt+1)][S]; the C-points (time points n = j*m0; every point when
+ * m0 <= 1) receive the seeded values, the other entries are left alone. */
+void slmo_seeded_iterate(uint64_t seed, int nt, long long S, int m0, double *u)
+{
+    int step = m0 > 1 ? m0 : 1;
+    for (long long n = 0; n <= nt; n += step)
+        for (long long k = 0; k < S; k++) u[n * S + k] = slmo_seeded_value(seed, (uint64_t)(n * S + k));
+}
+
 /* Level hierarchy (Sec. 2.2 and 3.4): coarsen by m_l while the coarse level
  * keeps at least two time points.  Reading: also stop at max_levels, once a
  * level has no more than coarsest_max_points points, or when N_l is not a
@@ -627,6 +687,7 @@ slmo_ctx *slmo_setup(const slmo_problem *pr, const slmo_solver *sv)
     /* level 0: ERK departure points of every fine step */
     c->dep[0][0] = alloc0(S * c->N[0]);
     c->dep[0][1] = dim == 2 ? alloc0(S * c->N[0]) : NULL;
+#pragma omp parallel for schedule(dynamic)
     for (int n = 0; n < c->N[0]; n++)
         slmo_depart_fine(pr, n, c->dep[0][0] + n * S, dim == 2 ? c->dep[0][1] + n * S : NULL);
 
@@ -639,6 +700,7 @@ slmo_ctx *slmo_setup(const slmo_problem *pr, const slmo_solver *sv)
         if (sv->coarse_op == SLMO_COARSE_REDISC) {
             /* rediscretised operator: departure points from M_l fine-size ERK
              * steps (Sec. 2.3; Sec. 4.3 locates them this way). */
+#pragma omp parallel for schedule(dynamic)
             for (long long n = 0; n < Nl; n++)
                 for (long long id = 0; id < S; id++) {
                     double x = -1.0 + (id % nx) * h, y = dim == 2 ? -1.0 + (id / nx) * h : 0.0;
@@ -660,6 +722,7 @@ slmo_ctx *slmo_setup(const slmo_problem *pr, const slmo_solver *sv)
         c->sig[l][0] = alloc0(S * Nl);
         c->sig[l][1] = dim == 2 ? alloc0(S * Nl) : NULL;
         double sgn = (p + 1) % 2 == 0 ? 1.0 : -1.0;
+#pragma omp parallel for schedule(dynamic)
         for (long long n = 0; n < Nl; n++) {
             const double *fx = c->dep[l - 1][0] + n * m * S;
             if (dim == 1) slmo_backtrack_1d(nx, m, fx, c->dep[l][0] + n * S);
@@ -746,7 +809,9 @@ void slmo_apply_phi(slmo_ctx *c, int l, int n, const double *in, double *out)
     int it = slmo_bsolve(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
                          pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL,
                          tmp, out, c->sv.gmres_kmax, c->sv.gmres_rtol);
+#pragma omp atomic
     c->gmres_solves++;
+#pragma omp atomic
     c->gmres_iters += it;
     free(tmp);
 }
@@ -775,6 +840,7 @@ static void step_to(slmo_ctx *c, int l, int n)
 static void f_relax(slmo_ctx *c, int l)
 {
     int m = c->mm[l], nc = c->N[l] / m;
+#pragma omp parallel for schedule(dynamic)
     for (int j = 0; j < nc; j++)
         for (int k = 1; k < m; k++) step_to(c, l, j * m + k);
 }
@@ -783,6 +849,7 @@ static void f_relax(slmo_ctx *c, int l)
 static void c_relax(slmo_ctx *c, int l)
 {
     int m = c->mm[l], nc = c->N[l] / m;
+#pragma omp parallel for schedule(dynamic)
     for (int j = 1; j <= nc; j++) step_to(c, l, j * m);
 }
 
@@ -794,15 +861,16 @@ static double residual(slmo_ctx *c, int l)
     int m = c->mm[l], nc = c->N[l] / m;
     long long S = c->S;
     double *v = c->v[l], *gc = c->g[l + 1], s2 = 0.0;
+#pragma omp parallel for schedule(dynamic)
     for (int j = 1; j <= nc; j++) {
         long long n = (long long)j * m;
-        phi_sys(c, l, (int)n - 1, v + (n - 1) * S, c->t0);
-        for (long long i = 0; i < S; i++) {
-            double r = (c->g[l] ? c->g[l][n * S + i] : 0.0) + c->t0[i] - v[n * S + i];
-            gc[(long long)j * S + i] = r;
-            s2 += r * r;
-        }
+        double *t = gc + (long long)j * S;            /* Phi v_{jm-1}, then r_{jm} */
+        phi_sys(c, l, (int)n - 1, v + (n - 1) * S, t);
+        for (long long i = 0; i < S; i++)
+            t[i] = (c->g[l] ? c->g[l][n * S + i] : 0.0) + t[i] - v[n * S + i];
     }
+    for (int j = 1; j <= nc; j++)                      /* in index order */
+        for (long long i = 0; i < S; i++) s2 += gc[(long long)j * S + i] * gc[(long long)j * S + i];
     return sqrt(s2);
 }
 
@@ -979,7 +1047,9 @@ void slmo_apply_phi_T(slmo_ctx *c, int l, int n, const double *in, double *out)
     int it = slmo_bsolve_T(pr->dim, pr->nx, pr->p, c->sig[l][0] + (long long)n * S,
                            pr->dim == 2 ? c->sig[l][1] + (long long)n * S : NULL,
                            in, tmp, c->sv.gmres_kmax, c->sv.gmres_rtol);
+#pragma omp atomic
     c->gmres_solves++;
+#pragma omp atomic
     c->gmres_iters += it;
     slmo_interp_T(pr->dim, pr->nx, pr->p, c->dep[l][0] + (long long)n * S,
                   pr->dim == 2 ? c->dep[l][1] + (long long)n * S : NULL, tmp, out);

@@ -61,6 +61,10 @@ typedef struct {
     long long gmres_solves, gmres_iters;
 } slmo_stats;
 
+/* ---- threads (OpenMP builds; results do not depend on the count) ---- */
+void slmo_set_threads(int n);
+int  slmo_get_threads(void);
+
 /* ---- scalar building blocks ---- */
 double slmo_wave(const slmo_term *t, int n, double x, double y, double time);
 int    slmo_erk_tableau(int r, double *c, double *a, double *b); /* a is 6x6 row-major */
@@ -92,6 +96,11 @@ void slmo_backtrack_1d(int nx, int m, const double *fine /* m x nx */, double *c
 void slmo_backtrack_2d(int nx, int m, const double *fxi, const double *feta,
                        double *cxi, double *ceta);
 void slmo_seq_fine(const slmo_problem *pr, const double *u0, double *u_all);
+
+/* ---- seeded initial iterate (Sec. 2.2: random initial guess) ---- */
+uint64_t slmo_splitmix64(uint64_t state);
+double   slmo_seeded_value(uint64_t seed, uint64_t idx);
+void     slmo_seeded_iterate(uint64_t seed, int nt, long long S, int m0, double *u);
 
 /* ---- hierarchy, setup and MGRIT ---- */
 typedef struct slmo_ctx slmo_ctx;

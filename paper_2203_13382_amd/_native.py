@@ -54,9 +54,11 @@ SIGNATURES = [
     ("slm_plan_levels", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]),
     ("slm_plan_setup", C.c_int, [_VP, _VP, C.c_size_t, _VP]),
     ("slm_level_arrays", C.c_int, [_VP, C.c_int, C.POINTER(_VP), C.POINTER(C.c_int), C.POINTER(_VP)]),
+    ("slm_launch_info", C.c_int, [_VP, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("slm_apply_phi", C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
     ("slm_relax", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]),
     ("slm_step", C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
+    ("slm_seed_iterate", C.c_int, [_VP, C.c_uint64, _VP, C.c_int, _VP]),
     ("slm_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats), C.POINTER(C.c_double), C.c_int, _VP]),
     ("slm_solve_cpoints", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats), C.POINTER(C.c_double), C.c_int, _VP]),
     ("slm_adjoint", C.c_int, [_VP, _VP, _VP, _VP, C.POINTER(C.c_double), C.POINTER(Stats),

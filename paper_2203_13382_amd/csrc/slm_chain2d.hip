@@ -506,9 +506,10 @@ hipError_t launch_step(int p, dim3 grid, hipStream_t st, const T *src, long long
 
 // Level-0 step, LDS-tiled when the window of a tile fits (F from the bound
 // on the displacement); the plain gather kernel otherwise.
-template <typename T, typename TD>
-hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src, long long ss, T *dst, long long ds,
-                        const TD *disp, long long plane, long long n_first, int stride, const T *G, T *Vout)
+// Halo F (cells) of the LDS-tiled level-0 step for a launch over nch
+// chains, or 0 when the plain gather kernel runs instead: the window must
+// fit in 48 KB and the launch must have enough tiles to fill the GPU.
+int step0_tile_halo(const slm_plan &P, int nch, size_t *lds_bytes)
 {
     const int nx = P.d.nx, p = P.d.p;
     double a = 0.0, b = 0.0;
@@ -517,9 +518,22 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
     const double dbound = P.d.dt / (2.0 / nx) * (a > b ? a : b);
     const int F = (int)std::ceil(dbound) + 1;
     const int wx = TILE_X + 2 * F + p / 2 + 1 + p / 2, wy = TILE_Y + 2 * F + p / 2 + 1 + p / 2;
-    const size_t lds = (size_t)wx * wy * sizeof(T);
+    const size_t lds = (size_t)wx * wy * P.elem;
     const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
-    if (F > 16 || lds > 48 * 1024 || (long long)ntiles * nch < 256) {   // too few tiles to fill the GPU
+    if (lds_bytes) *lds_bytes = lds;
+    if (F > 16 || lds > 48 * 1024 || (long long)ntiles * nch < 256) return 0;
+    return F;
+}
+
+template <typename T, typename TD>
+hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src, long long ss, T *dst, long long ds,
+                        const TD *disp, long long plane, long long n_first, int stride, const T *G, T *Vout)
+{
+    const int nx = P.d.nx, p = P.d.p;
+    size_t lds = 0;
+    const int F = step0_tile_halo(P, nch, &lds);
+    const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
+    if (F == 0) {
         const dim3 grid(nblocks((long long)nx * nx), nch);
         return launch_step<T, TD>(p, grid, st, src, ss, dst, ds, disp, plane, nx, n_first, stride, G, Vout);
     }
@@ -691,6 +705,13 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
 }  // namespace
 
 int chain2d_blocks(long long S) { return nblocks(S); }
+
+int chain2d_tiled(const slm_plan &P, int level, int nchains)
+{
+    if (level != 0 || P.adj_mode) return 0;
+    const int cap = P.cap2 > 0 ? P.cap2 : 1;
+    return step0_tile_halo(P, nchains < cap ? nchains : cap, nullptr) > 0 ? 1 : 0;
+}
 
 hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
 {

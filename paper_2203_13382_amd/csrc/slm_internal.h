@@ -98,9 +98,12 @@ hipError_t launch_trace_2d(const slm_plan &P, hipStream_t st);
 hipError_t launch_backtrack_2d(const slm_plan &P, int level, hipStream_t st);
 hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);
 int chain2d_blocks(long long S);
+int chain2d_tiled(const slm_plan &P, int level, int nchains);
 hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st);
 hipError_t launch_axpy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
                               int count, int S, int elem, int assign, hipStream_t st);
+hipError_t launch_seed_slices(void *u, long long ls, int count, int S, long long nstep, unsigned long long seed,
+                              int elem, hipStream_t st);
 hipError_t launch_copy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
                               int count, int S, int elem, hipStream_t st);
 // adjoint (slm_adjoint.hip)

@@ -29,7 +29,47 @@ __global__ void axpy_kernel(T *__restrict__ dst, long long ds, const T *__restri
     else dst[c * ds + id] += v;
 }
 
+// SplitMix64 output for the state x (Steele, Lea & Flood, OOPSLA 2014).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x)
+{
+    unsigned long long z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Seeded random initial iterate: slice c of u (stride ls elements) is fine
+// time point n = (c0 + c) * nstep and receives, at node k, the top 53 bits of
+// splitmix64(seed ^ (n*S + k)) as a fraction of 2^53 (rounded to T).
+template <typename T>
+__global__ void seed_kernel(T *__restrict__ u, long long ls, int c0, int count, long long S, long long nstep,
+                            unsigned long long seed)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (k >= S || c >= count) return;
+    const unsigned long long idx = (unsigned long long)((long long)(c0 + c) * nstep * S + k);
+    const double v = (double)(splitmix64(seed ^ idx) >> 11) * (1.0 / 9007199254740992.0);
+    u[(long long)(c0 + c) * ls + k] = T(v);
+}
+
 }  // namespace
+
+hipError_t launch_seed_slices(void *u, long long ls, int count, int S, long long nstep, unsigned long long seed,
+                              int elem, hipStream_t st)
+{
+    for (int c0 = 0; c0 < count; c0 += 65535) {           // grid.y limit
+        const int cnt = count - c0 < 65535 ? count - c0 : 65535;
+        dim3 grid((unsigned)((S + 255) / 256), (unsigned)cnt);
+        if (elem == 8)
+            hipLaunchKernelGGL(seed_kernel<double>, grid, dim3(256), 0, st, (double *)u, ls, c0, cnt, (long long)S,
+                               nstep, seed);
+        else
+            hipLaunchKernelGGL(seed_kernel<float>, grid, dim3(256), 0, st, (float *)u, ls, c0, cnt, (long long)S,
+                               nstep, seed);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st)
 {

@@ -475,6 +475,15 @@ int slm_level_arrays(const slm_plan *P, int level, const void **d_disp, int *dis
     return SLM_OK;
 }
 
+int slm_launch_info(const slm_plan *P, int level, int nchains, int *tiled, int *blocks_per_system)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (level < 0 || level >= P->L || nchains < 1) return fail(*P, SLM_EINVAL, "level or chain count out of range");
+    if (tiled) *tiled = P->d.dim == 2 ? chain2d_tiled(*P, level, nchains) : 0;
+    if (blocks_per_system) *blocks_per_system = P->d.dim == 2 ? P->nb2 : 1;
+    return SLM_OK;
+}
+
 int slm_apply_phi(slm_plan *P, int level, int n0, int count, const void *d_in, void *d_out, void *stream)
 {
     if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
@@ -560,6 +569,19 @@ int slm_step(slm_plan *P, const void *d_u0, void *d_u, int store_all, void *stre
         a.cout_shift = 0;
     }
     HIPCHK(chain(*P, 0, 1, a, (hipStream_t)stream));
+    return SLM_OK;
+}
+
+int slm_seed_iterate(slm_plan *P, uint64_t seed, void *d_u, int layout, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!d_u) return fail(P, SLM_EINVAL, "NULL pointer");
+    const int m0 = P->lv[0].m > 1 ? P->lv[0].m : 1, nc = P->d.nt / m0;
+    long long ls;
+    if (layout == SLM_ITERATE_FULL) ls = (long long)m0 * P->S;
+    else if (layout == SLM_ITERATE_CPOINTS) ls = P->S;
+    else return fail(P, SLM_EINVAL, "layout must be SLM_ITERATE_FULL or SLM_ITERATE_CPOINTS");
+    HIPCHK(launch_seed_slices(d_u, ls, nc + 1, P->S, m0, (unsigned long long)seed, P->elem, (hipStream_t)stream));
     return SLM_OK;
 }
 

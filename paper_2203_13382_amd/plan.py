@@ -90,6 +90,13 @@ class Plan:
             sig = self._view(ds.value, dim * Nl * self.S * 8, torch.float64, (dim, Nl, self.S))
         return disp, sig
 
+    def launch_info(self, level, nchains):
+        """(tiled, blocks_per_system) of level ``level``'s step over
+        ``nchains`` intervals (slm_launch_info)."""
+        t, b = C.c_int(), C.c_int()
+        N.check(N.lib().slm_launch_info(self.h, level, nchains, C.byref(t), C.byref(b)), self.h)
+        return t.value, b.value
+
     # ------------------------------------------------------------ operators
     def _dev(self, x):
         x = torch.as_tensor(x)
@@ -135,6 +142,14 @@ class Plan:
         shape = (self.pr.nt + 1, self.S) if store_all else (self.S,)
         u = torch.empty(shape, dtype=self.dtype, device=self.device)
         N.check(N.lib().slm_step(self.h, _ptr(u0), _ptr(u), int(store_all), _stream(stream)), self.h)
+        return u
+
+    def seed_iterate(self, u, seed, cpoints=False, stream=None):
+        """Write the seeded initial iterate (slm_seed_iterate) into the
+        C-points of ``u``: [nt+1][S] (``cpoints=False``) or [nt/m0+1][S]."""
+        assert u.dtype == self.dtype and u.is_contiguous()
+        N.check(N.lib().slm_seed_iterate(self.h, C.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), _ptr(u), int(bool(cpoints)),
+                                         _stream(stream)), self.h)
         return u
 
     def solve(self, u0, u, hist_cap=512, stream=None):

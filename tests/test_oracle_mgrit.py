@@ -142,3 +142,31 @@ def test_paper_table_3_rediscretised(oracle, row):
     stopping test must not cut such runs off as diverged."""
     it = _paper_iters(oracle, row, coarse_op="redisc")
     assert abs(it - row["redisc"]) <= 2, (row, it)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_thread_count_does_not_change_results(oracle, dim):
+    """The oracle's intervals may run on several threads; every sum keeps its
+    index order, so the results are bitwise those of one thread."""
+    if dim == 1:
+        pr = _prob(64, 256, 1.7, 3)
+    else:
+        a, b = W.field_cfg3()
+        pr = W.Problem(2, 16, 64, 2.0 * 2 / 16, 3, 3, a, b)
+    sv = W.Solver(m=[4], coarsest_max_points=2, gmres_rtol=1e-2)
+    u0 = I.initial_condition(pr, 0)
+    ui = oracle.seeded_iterate(3, pr.nt, pr.S, 4)
+    nthr = oracle.get_threads()
+    try:
+        out = []
+        for n in (1, 4):
+            oracle.set_threads(n)
+            ctx = oracle.Context(pr, sv)
+            u, st, hist = ctx.mgrit(u0, ui)
+            out.append((u, st, hist, ctx.dep(1, 0), ctx.sigma(1, 0)))
+    finally:
+        oracle.set_threads(nthr)
+    (u1, s1, h1, d1, g1), (u4, s4, h4, d4, g4) = out
+    assert np.array_equal(u1, u4) and np.array_equal(h1, h4)
+    assert np.array_equal(d1, d4) and np.array_equal(g1, g4)
+    assert s1 == s4
