@@ -177,6 +177,22 @@ int slm_relax(slm_plan *plan, int level, int mode, const void *d_g,
               const void *d_c_in, void *d_c_out, void *d_res, void *d_v,
               double *h_norm, void *stream);
 
+/* slm_relax for callers that cannot allocate device memory or bring a
+ * scratch workspace per call (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * kernels as slm_relax; the residual partial sums and the norm live in a
+ * static device array of the library (one per GPU, (SLM_NOALLOC_MAX_CHAINS
+ * + 32) doubles = 512.25 KiB, held until the process ends) instead of the
+ * plan's workspace, and the GMRES statistics counters are not updated.  The
+ * call allocates nothing.  Limits: 1D plans only (SLM_EUNSUPPORTED
+ * otherwise); at most SLM_NOALLOC_MAX_CHAINS intervals on the level
+ * (SLM_EINVAL otherwise, nothing launched).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams or host
+ * threads) race on it and must be serialised by the caller. */
+#define SLM_NOALLOC_MAX_CHAINS 65536
+int slm_relax_noalloc(slm_plan *plan, int level, int mode, const void *d_g, const void *d_c_in, void *d_c_out,
+                      void *d_res, void *d_v, double *h_norm, void *stream);
+
 /* Sequential time stepping: u_{n+1} = S_{p,r}(t_n) u_n for n = 0..nt-1
  * from d_u0 (T, [S]), i.e. forward substitution through the one-step
  * system (eq. one-step) with the fine SL step of Sec. 2.1 (Sec. 4.1 in 2D);

@@ -57,6 +57,7 @@ SIGNATURES = [
     ("slm_launch_info", C.c_int, [_VP, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("slm_apply_phi", C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
     ("slm_relax", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]),
+    ("slm_relax_noalloc", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]),
     ("slm_step", C.c_int, [_VP, _VP, _VP, C.c_int, _VP]),
     ("slm_seed_iterate", C.c_int, [_VP, C.c_uint64, _VP, C.c_int, _VP]),
     ("slm_solve", C.c_int, [_VP, _VP, _VP, C.POINTER(Stats), C.POINTER(C.c_double), C.c_int, _VP]),

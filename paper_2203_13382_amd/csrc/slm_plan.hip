@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "slm_internal.h"
@@ -543,6 +544,94 @@ int slm_relax(slm_plan *P, int level, int mode, const void *d_g, const void *d_c
     if (mode == SLM_SWEEP_RES && h_norm) {
         double *dn = (double *)ws_at(*P, P->norm);
         HIPCHK(sum_norm(*P, nc, dn, st));
+        double v = 0.0;
+        HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *h_norm = std::sqrt(v);
+    }
+    return SLM_OK;
+}
+
+// Scratch of slm_relax_noalloc: the per-interval residual partial sums
+// (SLM_NOALLOC_MAX_CHAINS doubles) followed by the norm.  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): it passes the address hipGetSymbolAddress returned
+// for the current device.
+static __device__ __align__(256) double scratch[SLM_NOALLOC_MAX_CHAINS + 32];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+hipError_t scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+int slm_relax_noalloc(slm_plan *P, int level, int mode, const void *d_g, const void *d_c_in, void *d_c_out,
+                      void *d_res, void *d_v, double *h_norm, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (P->d.dim != 1 || P->adj_mode)
+        return fail(P, SLM_EUNSUPPORTED, "slm_relax_noalloc supports 1D plans only (2D sweeps stage slices in the workspace)");
+    if (level < 0 || level >= P->L - 1) return fail(P, SLM_EINVAL, "level must have a coarser level below it");
+    hipStream_t st = (hipStream_t)stream;
+    const LevelInfo &L = P->lv[level];
+    const int m = L.m, nc = L.N / m;
+    if (nc > SLM_NOALLOC_MAX_CHAINS)
+        return fail(P, SLM_EINVAL, "slm_relax_noalloc: more than SLM_NOALLOC_MAX_CHAINS (65536) intervals on this level");
+    double *scr = nullptr;
+    HIPCHK(scratch_on_current_device(&scr));
+    ChainArgs a = base_args(*P, level);
+    a.counter = nullptr;                    // no GMRES statistics: nothing outside the inputs, outputs and scratch
+    a.G = d_g;
+    a.Cin = d_c_in;
+    if (mode == SLM_SWEEP_FC) {
+        if (!d_c_out) return fail(P, SLM_EINVAL, "c_out required");
+        a.nsteps = m;
+        a.Cout = d_c_out;
+    } else if (mode == SLM_SWEEP_RES) {
+        if (!d_res) return fail(P, SLM_EINVAL, "res required");
+        a.nsteps = m;
+        a.Cref = d_c_in;
+        a.R = d_res;
+        a.partial = scr;                    // every interval overwrites its own slot
+    } else if (mode == SLM_SWEEP_F) {
+        if (!d_v) return fail(P, SLM_EINVAL, "v required");
+        a.nsteps = m - 1;
+        a.Vout = d_v;
+        a.write_start = 1;
+        a.write_last = 1;
+    } else {
+        return fail(P, SLM_EINVAL, "bad mode");
+    }
+    HIPCHK(chain(*P, level, nc, a, st));
+    if (mode == SLM_SWEEP_F && d_c_in) {
+        HIPCHK(launch_copy_slices((char *)d_v + (size_t)L.N * P->S * P->elem, P->S,
+                                  (const char *)d_c_in + (size_t)nc * P->S * P->elem, P->S, 1, P->S, P->elem, st));
+    }
+    if (mode == SLM_SWEEP_RES && h_norm) {
+        double *dn = scr + SLM_NOALLOC_MAX_CHAINS;
+        HIPCHK(launch_sum_partials(scr, nc, dn, st));
         double v = 0.0;
         HIPCHK(hipMemcpyAsync(&v, dn, sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
