@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-bulk variant")
-    ap.add_argument("--cpu-nt", type=int, default=1024, help="time steps of the CPU oracle sample")
+    ap.add_argument("--cpu-nt", type=int, default=4096, help="time steps of the CPU oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
                     help="run only the level-0 F+C sweep kernel and a 1 GiB device copy (for counter runs)")
@@ -518,23 +518,96 @@ def main():
                             "max_rel_err_vs_fp64_seq": float((u32.double() - useq).abs().max() / useq.abs().max()),
                             "speedup_vs_fp64_seq": (trace_ms + seq_ms) / ms32}
 
+    # ---------------------------------------------------------------- per-level sweeps
+    out["levels"] = level_table(torch, plan, pr, "fp64", args.kernel_reps)
+
     # ---------------------------------------------------------------- CPU oracle baseline
     if not args.no_cpu:
-        from oracle import oracle as O
-        O.build(force=False)
-        prc = W.scaled(pr, pr.nx, args.cpu_nt, 4.0)
-        t0 = time.perf_counter()
-        ctx = O.Context(prc, sv)
-        u0c = I.initial_condition(prc, 0)
-        uic = I.initial_iterate(prc.nt, prc.S, sv.m[0], 1)
-        _, stc, _ = ctx.mgrit(u0c, uic)
-        tc = time.perf_counter() - t0
-        updc = updates_of(ctx.N, ctx.m, stc["iterations"], sv.relax == "FCF", ctx.L) * prc.S
-        out["cpu_baseline"] = {"value": updc / tc, "unit": "point-updates/s", "cores": 1, "kind": "oracle",
-                               "sample": f"same PDE and solver with nt={prc.nt} (1/{pr.nt // prc.nt} of the time "
-                                         f"domain): setup + MGRIT to rel. 1e-10, {stc['iterations']} iterations, "
-                                         f"{tc:.1f} s single-threaded; updates counted with the GPU schedule"}
+        out["cpu_baseline"] = cpu_baseline(pr, sv, args.cpu_nt)
     print(json.dumps(out))
+
+
+def level_table(torch, plan, pr, prec, reps):
+    """One F+C sweep on every level but the coarsest, timed with HIP events
+    on the launch stream: microseconds per sweep, point-updates per second,
+    and for level 0 the HBM rate of its algorithmic bytes (the displacement
+    of every update, the start C-points read and the new C-points written;
+    the slice stays on chip).  Coarse levels are latency-bound (GMRES with a
+    workgroup barrier per reduction), so their update rate is the figure."""
+    el = 8 if prec == "fp64" else 4
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rows = []
+    for l in range(plan.L - 1):
+        Nl, m = plan.N[l], plan.m[l]
+        nc = Nl // m
+        cin = torch.randn(nc + 1, pr.S, dtype=dt, device="cuda")
+        g = None if l == 0 else torch.randn(Nl + 1, pr.S, dtype=dt, device="cuda") * 1e-3
+        cout = torch.empty_like(cin)
+        us = timed(torch, lambda: plan.relax_into(l, "FC", c_in=cin, g=g, c_out=cout), reps) * 1e3
+        row = {"level": l, "steps": Nl, "intervals": nc, "sweep_us": us,
+               "point_updates_per_s": Nl * pr.S / (us * 1e-6)}
+        if l == 0:
+            b = el * pr.S * (Nl + 2 * nc + 1)
+            row.update({"bound": "hbm", "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
+                        "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS})
+        else:
+            row["bound"] = "latency"
+        rows.append(row)
+    return rows
+
+
+def cpu_threads():
+    """Host threads the oracle may use: the CPUs this process may run on,
+    at most 16 (one GPU's share of a host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pr, sv, cpu_nt):
+    """The FP64 oracle (unchanged) on a bounded sample of the same workload:
+    the same PDE and solver with nt = cpu_nt, setup + MGRIT to the
+    tolerance, once on one thread and once on every host thread it may use
+    (intervals in parallel, fixed-order sums; identical results)."""
+    from oracle import oracle as O
+    from paper_2203_13382_amd import inputs as I
+    from paper_2203_13382_amd import workloads as W
+    O.build(force=False)
+    prc = W.scaled(pr, pr.nx, cpu_nt, 4.0)
+    u0c = I.initial_condition(prc, 0)
+    uic = I.initial_iterate(prc.nt, prc.S, sv.m[0], 1)
+    res = {}
+    nthr = cpu_threads()
+    keep = O.get_threads()
+    try:
+        for n in (1, nthr):
+            O.set_threads(n)
+            t0 = time.perf_counter()
+            ctx = O.Context(prc, sv)
+            _, stc, _ = ctx.mgrit(u0c, uic)
+            res[n] = (time.perf_counter() - t0, stc, ctx)
+    finally:
+        O.set_threads(keep)
+    tc, stc, ctx = res[nthr]
+    updc = updates_of(ctx.N, ctx.m, stc["iterations"], sv.relax == "FCF", ctx.L) * prc.S
+    t1 = res[1][0]
+    return {"value": updc / tc, "unit": "point-updates/s", "cores": nthr, "kind": "oracle",
+            "single_thread_value": updc / t1, "cpu_model": cpu_model(),
+            "sample": f"same PDE and solver with nt={prc.nt} (1/{pr.nt // prc.nt} of the time domain): setup + "
+                      f"MGRIT to rel. 1e-10, {stc['iterations']} iterations; {tc:.1f} s on {nthr} threads, "
+                      f"{t1:.1f} s on 1 thread; updates counted with the GPU schedule"}
 
 
 if __name__ == "__main__":

@@ -412,10 +412,12 @@ static double dot(long long n, const double *a, const double *b)
 /* GMRES for [I - diag(sx)D_x - diag(sy)D_y] y = b with a zero initial guess
  * (Sec. 3.3: ten iterations; Sec. 3.4 and 4.3: stop once the relative
  * residual is at most 1e-2 or after ten iterations).  Reading: no
- * preconditioner; Arnoldi with classical Gram-Schmidt applied twice; Givens
- * rotations for the least-squares problem; the relative residual is the
- * Givens estimate |g_{j+1}|/||b||, tested after each iteration; rtol = 0 runs
- * all kmax iterations; b = 0 returns y = 0.  Returns the iterations done. */
+ * preconditioner; Arnoldi with classical Gram-Schmidt (one pass: every
+ * projection coefficient is taken of the same vector A v_j) and the new
+ * vector's norm computed from the vector itself; Givens rotations for the
+ * least-squares problem; the relative residual is the Givens estimate
+ * |g_{j+1}|/||b||, tested after each iteration; rtol = 0 runs all kmax
+ * iterations; b = 0 returns y = 0.  Returns the iterations done. */
 static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy,
                      const double *b, double *y, int kmax, double rtol, int transpose);
 
@@ -447,21 +449,17 @@ static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy
     double *sn = (double *)calloc(kmax, sizeof(double));
     double *g = (double *)calloc(kmax + 1, sizeof(double));
     double *hcol = (double *)calloc(kmax + 1, sizeof(double));
+    double *z = (double *)calloc(kmax + 1, sizeof(double));
     for (long long i = 0; i < S; i++) V[i] = b[i] / beta;
     g[0] = beta;
     int k = 0;
     for (int j = 0; j < kmax; j++) {
         if (transpose) slmo_apply_BT(dim, nx, p, sx, sy, V + (long long)j * S, w);
         else slmo_apply_B(dim, nx, p, sx, sy, V + (long long)j * S, w);
-        for (int i = 0; i <= j; i++) hcol[i] = 0.0;
-        for (int pass = 0; pass < 2; pass++) {       /* CGS, twice */
-            double hp[64];
-            for (int i = 0; i <= j; i++) hp[i] = dot(S, V + (long long)i * S, w);
-            for (int i = 0; i <= j; i++) {
-                const double *vi = V + (long long)i * S;
-                for (long long t = 0; t < S; t++) w[t] -= hp[i] * vi[t];
-                hcol[i] += hp[i];
-            }
+        for (int i = 0; i <= j; i++) hcol[i] = dot(S, V + (long long)i * S, w);   /* classical G-S */
+        for (int i = 0; i <= j; i++) {
+            const double *vi = V + (long long)i * S;
+            for (long long t = 0; t < S; t++) w[t] -= hcol[i] * vi[t];
         }
         double hn = sqrt(dot(S, w, w));
         for (int i = 0; i < j; i++) {                /* previous rotations */
@@ -481,7 +479,6 @@ static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy
         for (long long t = 0; t < S; t++) V[(long long)(j + 1) * S + t] = w[t] / hn;
         if (fabs(g[j + 1]) <= rtol * beta) break;
     }
-    double z[64];
     for (int i = k - 1; i >= 0; i--) {               /* back substitution */
         double s = g[i];
         for (int t = i + 1; t < k; t++) s -= H[(long long)t * (kmax + 1) + i] * z[t];
@@ -491,7 +488,7 @@ static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy
         const double *vi = V + (long long)i * S;
         for (long long t = 0; t < S; t++) y[t] += z[i] * vi[t];
     }
-    free(V); free(w); free(H); free(cs); free(sn); free(g); free(hcol);
+    free(V); free(w); free(H); free(cs); free(sn); free(g); free(hcol); free(z);
     return k;
 }
 

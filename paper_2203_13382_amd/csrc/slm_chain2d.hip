@@ -11,7 +11,8 @@
 // Coarse levels apply eq. (BEOper_2D) with the multilevel sigma of Sec. 4.3:
 //     v <- [I - diag(sx) D_x - diag(sy) D_y]^{-1} S_{p,r*} v,
 // D_x = I (x) D_{p+1}, D_y = D_{p+1} (x) I.  The inverse is applied by GMRES
-// (zero guess, classical Gram-Schmidt twice, Givens, exit at rtol or kmax),
+// (zero guess, classical Gram-Schmidt in one pass with the new vector's norm
+// reduced from the vector, Givens, exit at rtol or kmax),
 // batched over the chains: every Arnoldi phase is one launch over all
 // systems, inner products are per-block FP64 partial sums reduced in a fixed
 // order, and a one-thread-per-system kernel runs the Givens recurrence.
@@ -349,18 +350,17 @@ __global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__r
     if (threadIdx.x < nv) part_out[((long long)c * nb + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
-// Givens recurrence, one thread per system: h = pass-1 + pass-2
+// Givens recurrence, one thread per system: h = the Gram-Schmidt
 // coefficients, hn from the reduced norm (Sec. 3.3 GMRES, same arithmetic
 // order as the 1D kernel).
-__global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *h1, const double *h2, const double *nn,
-                          double rtol, int kmax)
+__global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *h1, const double *nn, double rtol, int kmax)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nsys) return;
     Gs2 &g = gs[c];
     if (g.done) return;
     double hc[SLM_KMAX + 1];
-    for (int i = 0; i <= j; ++i) hc[i] = h1[(long long)c * NPART + i] + h2[(long long)c * NPART + i];
+    for (int i = 0; i <= j; ++i) hc[i] = h1[(long long)c * NPART + i];
     const double hn = sqrt(nn[(long long)c * NPART]);
     for (int i = 0; i < j; ++i) {
         const double t0 = g.cs[i] * hc[i] + g.sn[i] * hc[i + 1];
@@ -665,12 +665,12 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                 if ((e = launch_matvec<T>(P.d.p, grid, st, V, W, S, nx, sig, plane, n_first0 + k, a.stride_chain, j, gs,
                                           pa, P.d.dim, a.adj, a.adj, L.N)) != hipSuccess)
                     return e;
+                // classical Gram-Schmidt: w -= V h with the projections of the
+                // matvec, then the partials of ||w||^2
                 hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, j + 1, gs, r1);
-                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, r1, pb, 1);
-                hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pb, nb, j + 1, gs, r2);
-                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, r2, pc, 0);
+                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, r1, pc, 0);
                 hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pc, nb, 1, gs, r3);
-                hipLaunchKernelGGL(g2_givens, dim3((nch + 63) / 64), dim3(64), 0, st, gs, nch, j, r1, r2, r3,
+                hipLaunchKernelGGL(g2_givens, dim3((nch + 63) / 64), dim3(64), 0, st, gs, nch, j, r1, r3,
                                    a.rtol, a.kmax);
                 hipLaunchKernelGGL(g2_normalize<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs);
             }

@@ -323,10 +323,9 @@ struct Gmres1D {
                 w[e] = T(0);
             }
         }
-        // classical Gram-Schmidt, twice; inner products are wave-uniform.
-        // The second pass also reduces ||w||^2, so ||w - V h2||^2 follows
-        // from Pythagoras (V orthonormal); an explicit reduction is used
-        // instead when that difference would cancel badly.
+        // classical Gram-Schmidt (every coefficient projects the same w);
+        // inner products are wave-uniform.  The new vector's norm is reduced
+        // from the updated vector itself.
         double h1[JJ + 1];
 #pragma unroll
         for (int i = 0; i <= JJ; ++i) {
@@ -344,43 +343,17 @@ struct Gmres1D {
             for (int i = 0; i <= JJ; ++i) t -= T(h1[i]) * V[i][e];
             w[e] = t;
         }
-        double h2[JJ + 2];
+        double nn[1] = {0.0};
 #pragma unroll
-        for (int i = 0; i <= JJ; ++i) {
-            double s = 0.0;
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) s += double(V[i][e] * w[e]);
-            h2[i] = s;
-        }
-        h2[JJ + 1] = 0.0;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) h2[JJ + 1] += double(w[e] * w[e]);
-        block_sum_u<JJ + 2>(h2, red, rb);
+        for (int e = 0; e < EPT; ++e) nn[0] += double(w[e] * w[e]);
+        block_sum_u<1>(nn, red, rb);
         rb ^= 1;
-#pragma unroll
-        for (int e = 0; e < EPT; ++e) {
-            T t = w[e];
-#pragma unroll
-            for (int i = 0; i <= JJ; ++i) t -= T(h2[i]) * V[i][e];
-            w[e] = t;
-        }
-        double hh = 0.0;
-#pragma unroll
-        for (int i = 0; i <= JJ; ++i) hh += h2[i] * h2[i];
-        double hn2 = h2[JJ + 1] - hh;
-        if (!(hh <= 0.5 * h2[JJ + 1])) {           // uniform branch
-            double nn[1] = {0.0};
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) nn[0] += double(w[e] * w[e]);
-            block_sum_u<1>(nn, red, rb);
-            rb ^= 1;
-            hn2 = nn[0];
-        }
+        const double hn2 = nn[0];
         const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
         if (tid == 0) {
             double hc[JJ + 1];
 #pragma unroll
-            for (int i = 0; i <= JJ; ++i) hc[i] = h1[i] + h2[i];
+            for (int i = 0; i <= JJ; ++i) hc[i] = h1[i];
 #pragma unroll
             for (int i = 0; i < JJ; ++i) {          // previous rotations
                 const double ci = gs->cs[i], si = gs->sn[i];

@@ -36,7 +36,7 @@ def main():
     out = os.path.join(HERE, "cfg2_oracle.txt")
     with open(out, "w") as f:
         f.write("# FP64 oracle, config-2 workload; written by tests/golden/make_cfg2_golden.py\n")
-        f.write(f"# oracle MGRIT wall time {t1 - t0:.1f} s (1 core)\n")
+        f.write(f"# oracle MGRIT wall time {t1 - t0:.1f} s ({O.get_threads()} threads)\n")
         f.write(f"levels {' '.join(str(n) for n in ctx.N)}\n")
         f.write(f"iterations {st['iterations']}\nstatus {st['status']}\n")
         f.write(f"gmres_solves {st['gmres_solves']}\ngmres_iters {st['gmres_iters']}\n")

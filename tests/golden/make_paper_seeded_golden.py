@@ -6,7 +6,8 @@ cycle by cycle on identical inputs.
 Cells: Tables 1 and 2 on the 2^8 x 2^10 mesh (every alpha, p and m), and
 Table 3 on the (2^6)^2 x 2^10 mesh with the modified coarse operator and
 with the rediscretized one (the counts in parentheses).  Each line holds the
-cell, the iteration count, the status and the residual history rho_k.
+cell, the iteration count, the status, the number of coarse solves and of
+GMRES iterations, and the residual history rho_k.
 
 Only the oracle is called.  Run from the repository root:
     python tests/golden/make_paper_seeded_golden.py [workers]
@@ -47,7 +48,8 @@ def run(cell):
     ui = O.seeded_iterate(SEED, pr.nt, pr.S, m0)
     _, st, hist = ctx.mgrit(u0, ui)
     m = "-".join(str(x) for x in r["m"]) if isinstance(r["m"], list) else str(r["m"])
-    head = f"{r['table']} {r['field']} {r['p']} {r['nx']} {r['nt']} {m} {op} {SEED} {st['iterations']} {st['status']}"
+    head = (f"{r['table']} {r['field']} {r['p']} {r['nx']} {r['nt']} {m} {op} {SEED} {st['iterations']} "
+            f"{st['status']} {st['gmres_solves']} {st['gmres_iters']}")
     line = head + " " + " ".join(f"{h:.17g}" for h in hist)
     print(head, flush=True)
     return line
@@ -68,7 +70,8 @@ def main():
     with open(OUT, "w") as f:
         f.write("# Oracle MGRIT runs of the paper's iteration-count cells from the seeded\n"
                 "# initial iterate (seed 5); written by make_paper_seeded_golden.py.\n"
-                "#   table field p nx nt m coarse_op seed iterations status rho_0 rho_1 ...\n")
+                "#   table field p nx nt m coarse_op seed iterations status gmres_solves gmres_iters\n"
+                "#   rho_0 rho_1 ...\n")
         for line in res:
             f.write(line + "\n")
     print("wrote", OUT)

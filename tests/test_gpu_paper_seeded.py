@@ -30,8 +30,8 @@ def _cells():
         f = line.split()
         m = [int(x) for x in f[5].split("-")] if "-" in f[5] else int(f[5])
         out.append(dict(table=f[0], field=f[1], p=int(f[2]), nx=int(f[3]), nt=int(f[4]), m=m, op=f[6],
-                        seed=int(f[7]), iterations=int(f[8]), status=f[9],
-                        hist=np.array([float(x) for x in f[10:]])))
+                        seed=int(f[7]), iterations=int(f[8]), status=f[9], gmres_solves=int(f[10]),
+                        gmres_iters=int(f[11]), hist=np.array([float(x) for x in f[12:]])))
     return out
 
 
@@ -80,16 +80,15 @@ def test_paper_cell_matches_oracle(cell, torch):
     h = cell["hist"]
     assert st["status"] == cell["status"]
     assert st["iterations"] == cell["iterations"]
-    # rho_k agree to 1e-6 relative while they are above 1e-7 of the largest
-    # one.  Below that, C-points that are already exact carry only rounding
-    # noise, which each side forms in its own order and which the coarse
-    # solves then propagate; the last rho_k of a run (~1e-10 rho_0) differ by
-    # up to ~1e-11 rho_0 (measured: 9e-12 rho_0 on the (2^6)^2, m = 16, p = 1
-    # cell), so they are held to 1e-10 of the largest rho_k.
-    big = h > 1e-7 * h.max()
-    bound = np.where(big, 1e-6 * h, 1e-10 * h.max())
+    # rho_k agree to 1e-6 relative plus 1e-10 of the largest rho_k.  The two
+    # sides round differently (summation orders, the new Arnoldi vector's
+    # norm), and the coarse solves carry such differences through the cycles:
+    # on the m = 16, p = 1 cells they grow to ~1.5e-11 of rho_0 by cycle 6,
+    # when rho_6 is ~1e-7 rho_0, then decay with the error.
+    bound = 1e-6 * h + 1e-10 * h.max()
     worst = (np.abs(hist - h) / bound).max()
     print(f"{_id(cell)}: GPU {st['iterations']} cycles, oracle {cell['iterations']}; "
-          f"worst history deviation {worst:.2f} of the bound")
+          f"worst history deviation {worst:.2f} of the bound; GMRES iterations {st['gmres_iters']} "
+          f"(oracle {cell['gmres_iters']})")
     assert worst <= 1.0, "\n".join(f"k={k} rho_k/max {h[k] / h.max():.3e} rel.dev {abs(hist[k] / h[k] - 1):.2e}"
                                     for k in range(len(h)))

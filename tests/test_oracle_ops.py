@@ -231,10 +231,35 @@ def test_modified_coarse_operator_truncation_order(oracle, p):
         Sc = oracle.interp(1, nx, p, xc, None, u)
         phi = (-1) ** (p + 1) * (oracle.fpoly(p, oracle.decompose(nx, xc[0])[1]) - fs)
         sig = np.full(nx, phi)
-        BSc, _ = oracle.bsolve(1, nx, p, sig, None, Sc, 400, 1e-15)
+        B = np.stack([oracle.apply_B(1, nx, p, sig, None, e) for e in np.eye(nx)], axis=1)
+        BSc = np.linalg.solve(B, Sc)                   # the exact inverse of B
         res_I.append(np.abs(v - Sc).max() / abs(phi))
         res_B.append(np.abs(v - BSc).max() / abs(phi))
     oI = [math.log2(res_I[i] / res_I[i + 1]) for i in range(3)]
     oB = [math.log2(res_B[i] / res_B[i + 1]) for i in range(3)]
     assert np.mean(oI[1:]) > p + 1 - 0.3, oI
     assert np.mean(oB[1:]) > p + 2 - 0.3, oB
+
+
+@pytest.mark.parametrize("dim,p,k", [(1, 1, 3), (1, 3, 5), (1, 5, 6), (2, 3, 4)])
+def test_gmres_iterate_minimises_residual_over_krylov_space(oracle, dim, p, k):
+    """After k iterations (rtol = 0) GMRES returns the minimiser of
+    ||b - B y|| over the Krylov space span{b, Bb, ..., B^{k-1} b} (the
+    definition of GMRES, Sec. 3.3), computed here by a least-squares solve
+    on the explicit power basis."""
+    nx = 12
+    S = nx if dim == 1 else nx * nx
+    rng = np.random.default_rng(5 + k)
+    sgn = (-1) ** ((p + 1) // 2 + 1)
+    sx = rng.uniform(0.0, 0.3, S) * sgn
+    sy = rng.uniform(0.0, 0.3, S) * sgn if dim == 2 else None
+    B = np.stack([oracle.apply_B(dim, nx, p, sx, sy, e) for e in np.eye(S)], axis=1)
+    b = rng.standard_normal(S)
+    K = [b]
+    for _ in range(k - 1):
+        K.append(B @ K[-1])
+    Q, _ = np.linalg.qr(np.stack(K, axis=1))
+    c, *_ = np.linalg.lstsq(B @ Q, b, rcond=None)
+    y, it = oracle.bsolve(dim, nx, p, sx, sy, b, k, 0.0)
+    assert it == k
+    assert np.abs(y - Q @ c).max() < 1e-10 * np.abs(Q @ c).max()

@@ -79,6 +79,6 @@ def test_seeded_golden_reproduces_the_printed_counts():
         want = r["redisc"] if f[6] == "redisc" else r["iters"]
         it = int(f[8])
         assert f[9] == "converged" and abs(it - want) <= 1, (f[:10], want)
-        assert len(f) - 10 == it                      # one residual per cycle
+        assert len(f) - 12 == it                      # one residual per cycle
         exact += it == want
     assert exact >= 81
