@@ -555,6 +555,7 @@ hipError_t launch_grad(const slm_plan &P, int nch, const double *U, long long u_
     const dim3 grid(P.nb2, nch);                 // gacc holds P.nb2 slots per interval
     const double h = 2.0 / P.d.nx;
     const int c0 = (int)(n_first / stride);
+    if (!slots_fit(P, (int)grid.x, c0, nch, P.lv[0].N / P.lv[0].m)) return kSlotMismatch;
 #define GK(PP, RR, DD) hipLaunchKernelGGL((grad_kernel<PP, RR, DD>), grid, dim3(TPB), 0, st, U, u_stride, lam, \
                                           lam_stride, disp, (long long)P.lv[0].N * S, P.d.nx, S, n_first, stride, \
                                           P.d.dt, h, P.fa, P.fb, P.nq, gacc, c0)

@@ -598,6 +598,10 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
     T *bufs[2] = {Wb, Wb + (long long)P.cap2 * S};
     const int nb = nblocks(S);
     dim3 grid(nb, nch);
+    // slots: the residual partials (part2) hold cap2 intervals, the GMRES
+    // partials capg systems
+    if ((a.R && !slots_fit(P, nb, c0, nch, P.cap2)) || (level > 0 && !slots_fit(P, nb, 0, nch, P.capg)))
+        return kSlotMismatch;
     const long long n_first0 = a.n_base + (long long)c0 * a.stride_chain;
     const T *Cin = a.Cin ? (const T *)a.Cin + (long long)c0 * a.cin_stride : nullptr;
     T *Vout = (T *)a.Vout;

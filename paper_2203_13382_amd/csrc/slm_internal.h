@@ -122,3 +122,14 @@ hipError_t launch_fill0(double *p, long long n, hipStream_t st);
 void slm_set_error(const std::string &msg);
 
 inline char *ws_at(const slm_plan &P, size_t off) { return P.ws + off; }
+
+// Per-(interval, block) slot buffers (residual and GMRES partial sums, the
+// adjoint's gradient slots) are sized for P.nb2 blocks per interval and a
+// fixed number of intervals.  A launcher whose grid would index past them
+// returns this code instead of launching; the C ABI reports it as
+// SLM_EINVAL.
+constexpr hipError_t kSlotMismatch = hipErrorInvalidValue;
+inline bool slots_fit(const slm_plan &P, int nb, long long first_interval, long long count, long long capacity)
+{
+    return nb == P.nb2 && first_interval >= 0 && count >= 0 && first_interval + count <= capacity;
+}

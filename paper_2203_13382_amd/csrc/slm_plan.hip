@@ -15,6 +15,9 @@ namespace {
 #define HIPCHK(expr)                                                                  \
     do {                                                                              \
         hipError_t e_ = (expr);                                                       \
+        if (e_ == kSlotMismatch)                                                      \
+            return fail(P, SLM_EINVAL, std::string(#expr) + ": launch shape does not match the " \
+                                       "workspace's per-block slots (nothing launched)"); \
         if (e_ != hipSuccess) return fail(P, SLM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
@@ -453,6 +456,14 @@ int slm_plan_setup(slm_plan *P, void *d_ws, size_t bytes, void *stream)
     if (!d_ws || bytes < P->ws_bytes) return fail(P, SLM_EWORKSPACE, "workspace smaller than slm_plan_workspace_size()");
     if (((uintptr_t)d_ws & 255) != 0) return fail(P, SLM_EWORKSPACE, "workspace must be 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
+    // Setup and sweep launches put time steps, coarse steps or intervals on
+    // grid.y (at most nt of them); gfx950 takes up to 2^31-1 there, but a
+    // device that reports less is refused here rather than at a launch.
+    int dev = 0, maxy = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&maxy, hipDeviceAttributeMaxGridDimY, dev));
+    if (P->d.nt > maxy)
+        return fail(P, SLM_EUNSUPPORTED, "nt exceeds the device's grid.y limit (" + std::to_string(maxy) + ")");
     P->ws = (char *)d_ws;
     P->ready = false;
     P->adj_ready = false;                   // the inverse stencil index follows the departure points

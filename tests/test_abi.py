@@ -186,3 +186,32 @@ def test_fwd_euler_descriptor_validation():
         assert got == rc, (prob.p, prec, adj, got)
         if got == 0:
             L.slm_plan_destroy(h)
+
+
+@pytest.mark.parametrize("nx,nt,m", [(13, 24, [2, 3]), (20, 48, [4]), (64, 512, [8]), (100, 64, [4]),
+                                     (512, 64, [8]), (1000, 16, [4]), (2048, 32, [8])])
+def test_2d_per_block_slots_fit_the_workspace(nx, nt, m):
+    """Sizing of the per-(interval, block) slot buffers of the 2D path, on
+    the host: the batched kernels run ceil(S / 1024) workgroups per slice
+    (at most 1024), and the workspace holds one residual partial per
+    (interval, block) for the largest sweep and three GMRES partial sets of
+    16 per (system, block) for the largest coarse sweep."""
+    a, b = W.field_cfg3()
+    pr = W.Problem(2, nx, nt, 2.0 * 2 / nx, 3, 3, a, b)
+    rc, h, _ = _create(pr, W.Solver(m=m, coarsest_max_points=2))
+    assert rc == 0
+    try:
+        S = nx * nx
+        tiled, nb = C.c_int(), C.c_int()
+        assert N.lib().slm_launch_info(h, 0, 1, C.byref(tiled), C.byref(nb)) == 0
+        assert nb.value == min(1024, -(-S // 1024))
+        Ns, ms = _levels(h)
+        cap2 = max([Ns[l] // ms[l] for l in range(len(Ns)) if ms[l]] + [1])
+        capg = max([Ns[l] // ms[l] for l in range(1, len(Ns)) if ms[l]] + [1])
+        wsb = C.c_size_t()
+        assert N.lib().slm_plan_workspace_size(h, C.byref(wsb)) == 0
+        assert wsb.value >= 8 * nb.value * (cap2 + 3 * 16 * capg)
+        # the level-0 step of a one-slice call over many tiles never exceeds them
+        assert N.lib().slm_launch_info(h, len(Ns), 1, None, None) == -1
+    finally:
+        N.lib().slm_plan_destroy(h)
