@@ -233,7 +233,7 @@ def twod_bench(args):
     stream = torch.cuda.current_stream()
     u0 = torch.from_numpy(I.initial_condition(pr, 0)).cuda()
     ui = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 1).astype(np.float32)).cuda()
-    plan = Plan(pr, sv, prec)
+    plan = Plan(pr, sv, prec).setup().autotune()
     u = torch.empty_like(ui)
     u032 = u0.float()
     r = {}
@@ -278,6 +278,15 @@ def twod_bench(args):
         "seq": {"fp64_ms": seq_ms, "fp32_ms": seq32_ms},
         "speedup_vs_fp32_seq": seq32_ms / ms,
     }
+    levels = level_table(torch, plan, pr, prec, 5)
+    l0 = levels[0]
+    tiled, nb = plan.launch_info(0, plan.N[0] // plan.m[0])
+    out["levels"] = levels
+    out["roofline"] = {"kernel": f"level-0 F+C sweep (LDS-tiled SL steps, tile choice {plan.tile_choice()})"
+                                 if tiled else "level-0 F+C sweep (gather SL steps)",
+                       "bound": "hbm", "achieved": l0["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": l0["frac"], "traffic": None, "launch_ms": l0["sweep_us"] * 1e-3,
+                       "bytes_per_launch": l0["bytes"]}
     print(json.dumps(out))
 
 
@@ -428,7 +437,7 @@ def main():
     ui = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 1)).to(dev)
 
     # ---------------------------------------------------------------- FP64 MGRIT
-    plan = Plan(pr, sv, "fp64")
+    plan = Plan(pr, sv, "fp64").setup().autotune()
     u = torch.empty_like(ui)
     last = {}
 
@@ -499,7 +508,7 @@ def main():
     if not args.no_fp32:
         import dataclasses
         sv32 = dataclasses.replace(sv, tol=1e-6)
-        p32 = Plan(pr, sv32, "fp32")
+        p32 = Plan(pr, sv32, "fp32").setup().autotune()
         u32 = torch.empty(ui.shape, dtype=torch.float32, device=dev)
         ui32 = ui.float()
         u032 = u0.float()
@@ -547,7 +556,10 @@ def level_table(torch, plan, pr, prec, reps):
         row = {"level": l, "steps": Nl, "intervals": nc, "sweep_us": us,
                "point_updates_per_s": Nl * pr.S / (us * 1e-6)}
         if l == 0:
-            b = el * pr.S * (Nl + 2 * nc + 1)
+            if pr.dim == 1:     # displacement per update; start and new C-point per interval
+                b = el * pr.S * (Nl + 2 * nc + 1)
+            else:               # two displacements, the previous slice and the new one per update
+                b = el * pr.S * (4 * Nl + 2 * nc)
             row.update({"bound": "hbm", "bytes": b, "GBps": b / (us * 1e-6) / 1e9,
                         "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS})
         else:

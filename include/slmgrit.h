@@ -144,11 +144,29 @@ int slm_plan_setup(slm_plan *plan, void *d_ws, size_t bytes, void *stream);
 int slm_level_arrays(const slm_plan *plan, int level, const void **d_disp,
                      int *disp_is_f32, const void **d_sigma);
 
+/* Launch-shape autotuner of one plan.  Times the level-0 F+C relaxation
+ * sweep (Sec. 2.2) for a few launch shapes and keeps the fastest: in 2D the
+ * output tile of the LDS-staged SL step (Sec. 4.1; 64x16, 64x32, 128x16 or
+ * 128x32 nodes), in 1D the elements per thread and the slice
+ * double-buffering of level-0 sweeps that form no residual.  Every shape
+ * computes the same products in the same order, so results are bitwise
+ * independent of the choice (residual sweeps keep their built-in layout,
+ * whose per-interval sums follow the thread layout).  Needs setup
+ * (SLM_ENOTSETUP otherwise); d_ws is the workspace bound at setup or NULL,
+ * anything else is SLM_EINVAL; the plan's C-point buffers serve as timing
+ * scratch (no solve may run on the plan meanwhile).  With a non-NULL
+ * cache_path the choice is read from that text file when a line for this
+ * plan's shape exists, else measured and appended (one line per shape).
+ * Plans without coarsening, and adjoint plans, keep the built-in shapes.
+ * Synchronises `stream`. */
+int slm_autotune(slm_plan *plan, void *d_ws, size_t bytes, const char *cache_path, void *stream);
+
 /* Launch shape of level l's relaxation step (the SL step of Sec. 2.1 /
  * 4.1 on level 0, eq. (BEOper_2D) on coarse levels) for a call over
- * `nchains` intervals or slices, for tests and profiling: *tiled = 1 when
- * the 2D level-0 step stages each tile's source window in LDS (0: the plain
- * gather kernel; always 0 in 1D and on coarse levels); *blocks_per_system =
+ * `nchains` intervals or slices, for tests and profiling: *tiled = 1 + the
+ * tile shape index (see slm_autotune) when the 2D level-0 step stages each
+ * tile's source window in LDS (0: the plain gather kernel; always 0 in 1D
+ * and on coarse levels); *blocks_per_system =
  * workgroups per slice of the batched 2D kernels, whose per-block partial
  * sums are reduced in a fixed order (1 in 1D).  Either pointer may be NULL.
  * Host only. */

@@ -54,6 +54,7 @@ SIGNATURES = [
     ("slm_plan_levels", C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int]),
     ("slm_plan_setup", C.c_int, [_VP, _VP, C.c_size_t, _VP]),
     ("slm_level_arrays", C.c_int, [_VP, C.c_int, C.POINTER(_VP), C.POINTER(C.c_int), C.POINTER(_VP)]),
+    ("slm_autotune", C.c_int, [_VP, _VP, C.c_size_t, C.c_char_p, _VP]),
     ("slm_launch_info", C.c_int, [_VP, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("slm_apply_phi", C.c_int, [_VP, C.c_int, C.c_int, C.c_int, _VP, _VP, _VP]),
     ("slm_relax", C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP, _VP, _VP, _VP, C.POINTER(C.c_double), _VP]),

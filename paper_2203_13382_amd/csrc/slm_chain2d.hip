@@ -92,15 +92,19 @@ __global__ void __launch_bounds__(TPB) step2d_kernel(const T *__restrict__ src, 
 // stencils read only the window [x0 - F - LO, x0 + TX - 1 + F + HI] x (same in
 // y), loaded once with coalesced reads.  The (p+1)^2-tap gathers then hit LDS
 // instead of the texture path.  A stencil outside the window (not expected)
-// falls back to global reads, so the result never depends on F.
-constexpr int TILE_X = 64, TILE_Y = 16;
+// falls back to global reads, so the result never depends on F, and every
+// output is formed by the same products in the same order whatever the tile
+// shape (the autotuner's choice, slm_autotune).
+struct TileShape { int tx, ty; };
+constexpr TileShape kTiles[] = {{64, 16}, {64, 32}, {128, 16}, {128, 32}};
+constexpr int kNumTiles = 4;
 
-template <typename T, typename TD, int P>
+template <typename T, typename TD, int P, int TX, int TY>
 __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ src, long long src_stride,
                                                           T *__restrict__ dst, long long dst_stride,
                                                           const TD *__restrict__ disp, long long plane, int nx,
                                                           long long n_first, int stride, const T *__restrict__ G,
-                                                          T *__restrict__ Vout, int F)
+                                                          T *__restrict__ Vout, int F, unsigned inv_wx)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *win = reinterpret_cast<T *>(smem_raw);
@@ -109,18 +113,25 @@ __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ 
     const int c = blockIdx.y;
     const long long n = n_first + (long long)c * stride;
     const T *s = src + c * src_stride;
-    const int ntx = (nx + TILE_X - 1) / TILE_X;
-    const int x0 = (int)(blockIdx.x % ntx) * TILE_X, y0 = (int)(blockIdx.x / ntx) * TILE_Y;
-    const int wx = TILE_X + 2 * F + LO + HI, wy = TILE_Y + 2 * F + LO + HI;
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (int)(blockIdx.x % ntx) * TX, y0 = (int)(blockIdx.x / ntx) * TY;
+    const int wx = TX + 2 * F + LO + HI, wy = TY + 2 * F + LO + HI;
     const int ox = x0 - F - LO, oy = y0 - F - LO;   // window origin (unwrapped)
+    // Every window coordinate lies in (-nx, 2 nx) (checked on the host), so
+    // one conditional add or subtract wraps it; k / wx is a multiply by a
+    // 24-bit reciprocal, exact for k < wx * wy.
     for (int k = threadIdx.x; k < wx * wy; k += TPB) {
-        const int r = k / wx, q = k - r * wx;
-        const int gy = wrap_mod(oy + r, nx), gx = wrap_mod(ox + q, nx);
+        const int r = (int)(((unsigned long long)(unsigned)k * inv_wx) >> 24), q = k - r * wx;
+        int gy = oy + r, gx = ox + q;
+        gy += gy < 0 ? nx : 0;
+        gy -= gy >= nx ? nx : 0;
+        gx += gx < 0 ? nx : 0;
+        gx -= gx >= nx ? nx : 0;
         win[k] = s[(long long)gy * nx + gx];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < TILE_X * TILE_Y; k += TPB) {
-        const int ly = k / TILE_X, lx = k - ly * TILE_X;
+    for (int k = threadIdx.x; k < TX * TY; k += TPB) {
+        const int ly = k / TX, lx = k - ly * TX;
         const int i = x0 + lx, j = y0 + ly;
         if (i >= nx || j >= nx) continue;
         const long long id = (long long)j * nx + i;
@@ -506,22 +517,30 @@ hipError_t launch_step(int p, dim3 grid, hipStream_t st, const T *src, long long
 
 // Level-0 step, LDS-tiled when the window of a tile fits (F from the bound
 // on the displacement); the plain gather kernel otherwise.
-// Halo F (cells) of the LDS-tiled level-0 step for a launch over nch
-// chains, or 0 when the plain gather kernel runs instead: the window must
-// fit in 48 KB and the launch must have enough tiles to fill the GPU.
-int step0_tile_halo(const slm_plan &P, int nch, size_t *lds_bytes)
+// Halo F (cells) of the LDS-tiled level-0 step with tile shape `tile` for a
+// launch over nch chains, or 0 when the plain gather kernel runs instead:
+// every window coordinate must wrap onto the mesh with one add or subtract,
+// the window fit in 48 KB, and the launch have enough tiles to fill the GPU.
+int step0_tile_halo(const slm_plan &P, int tile, int nch, size_t *lds_bytes, int *wx_out)
 {
     const int nx = P.d.nx, p = P.d.p;
+    const TileShape ts = kTiles[tile >= 0 && tile < kNumTiles ? tile : 0];
     double a = 0.0, b = 0.0;
     for (const auto &t : P.alpha) a += std::fabs(t.coef);
     for (const auto &t : P.beta) b += std::fabs(t.coef);
     const double dbound = P.d.dt / (2.0 / nx) * (a > b ? a : b);
     const int F = (int)std::ceil(dbound) + 1;
-    const int wx = TILE_X + 2 * F + p / 2 + 1 + p / 2, wy = TILE_Y + 2 * F + p / 2 + 1 + p / 2;
+    const int wx = ts.tx + 2 * F + p / 2 + 1 + p / 2, wy = ts.ty + 2 * F + p / 2 + 1 + p / 2;
     const size_t lds = (size_t)wx * wy * P.elem;
-    const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
+    const int ntx = (nx + ts.tx - 1) / ts.tx, nty = (nx + ts.ty - 1) / ts.ty;
+    const long long ntiles = (long long)ntx * nty;
     if (lds_bytes) *lds_bytes = lds;
-    if (F > 16 || lds > 48 * 1024 || (long long)ntiles * nch < 256) return 0;
+    if (wx_out) *wx_out = wx;
+    // every window coordinate lies in (-nx, 2 nx), so the kernel wraps it
+    // with one conditional add or subtract
+    const int lo = p / 2 + 1, hi = p / 2;
+    const bool one_wrap = F + lo < nx && ntx * ts.tx + F + hi < 2 * nx && nty * ts.ty + F + hi < 2 * nx;
+    if (F > 16 || !one_wrap || lds > 48 * 1024 || ntiles * nch < 256) return 0;
     return F;
 }
 
@@ -531,22 +550,33 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
 {
     const int nx = P.d.nx, p = P.d.p;
     size_t lds = 0;
-    const int F = step0_tile_halo(P, nch, &lds);
-    const int ntiles = ((nx + TILE_X - 1) / TILE_X) * ((nx + TILE_Y - 1) / TILE_Y);
+    int wx = 1;
+    const int tile = P.tile2d >= 0 && P.tile2d < kNumTiles ? P.tile2d : 0;
+    const int F = step0_tile_halo(P, tile, nch, &lds, &wx);
     if (F == 0) {
         const dim3 grid(nblocks((long long)nx * nx), nch);
         return launch_step<T, TD>(p, grid, st, src, ss, dst, ds, disp, plane, nx, n_first, stride, G, Vout);
     }
-    const dim3 grid(ntiles, nch);
-#define STEPT(PP) hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP>), grid, dim3(TPB), lds, st, src, ss, dst, ds, disp, \
-                                     plane, nx, n_first, stride, G, Vout, F)
-    switch (p) {
-    case 1: STEPT(1); break;
-    case 2: STEPT(2); break;
-    case 3: STEPT(3); break;
-    case 4: STEPT(4); break;
-    default: STEPT(5); break;
+    const TileShape ts = kTiles[tile];
+    const dim3 grid(((nx + ts.tx - 1) / ts.tx) * ((nx + ts.ty - 1) / ts.ty), nch);
+    const unsigned inv_wx = (unsigned)(((1u << 24) + wx - 1) / wx);     // ceil(2^24 / wx)
+#define STEPT(PP, TXX, TYY) hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP, TXX, TYY>), grid, dim3(TPB), lds, st, src, \
+                                               ss, dst, ds, disp, plane, nx, n_first, stride, G, Vout, F, inv_wx)
+#define STEPP(TXX, TYY)                                       \
+    switch (p) {                                              \
+    case 1: STEPT(1, TXX, TYY); break;                        \
+    case 2: STEPT(2, TXX, TYY); break;                        \
+    case 3: STEPT(3, TXX, TYY); break;                        \
+    case 4: STEPT(4, TXX, TYY); break;                        \
+    default: STEPT(5, TXX, TYY); break;                       \
     }
+    switch (tile) {
+    case 1: STEPP(64, 32); break;
+    case 2: STEPP(128, 16); break;
+    case 3: STEPP(128, 32); break;
+    default: STEPP(64, 16); break;
+    }
+#undef STEPP
 #undef STEPT
     return hipGetLastError();
 }
@@ -714,8 +744,11 @@ int chain2d_tiled(const slm_plan &P, int level, int nchains)
 {
     if (level != 0 || P.adj_mode) return 0;
     const int cap = P.cap2 > 0 ? P.cap2 : 1;
-    return step0_tile_halo(P, nchains < cap ? nchains : cap, nullptr) > 0 ? 1 : 0;
+    const int tile = P.tile2d >= 0 && P.tile2d < kNumTiles ? P.tile2d : 0;
+    return step0_tile_halo(P, tile, nchains < cap ? nchains : cap, nullptr, nullptr) > 0 ? 1 + tile : 0;
 }
+
+int chain2d_num_tiles() { return kNumTiles; }
 
 hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st)
 {

@@ -33,10 +33,18 @@ hipError_t launch(K kern, int nchains, int block, size_t lds, const ChainArgs &a
     return hipGetLastError();
 }
 
+// The autotuner's elements per thread apply to sweeps over many intervals
+// (the shape it timed) that form no residual: with a residual the per-chain
+// sum of squares follows the thread layout, so those sweeps keep the
+// built-in shape and the norms stay bitwise fixed.
 template <typename T, typename TD, int P, bool DBUF>
 hipError_t fine_ept(const ChainArgs &a, int nchains, hipStream_t st)
 {
-    const int block = fine_block(a.nx, nchains);
+    int block = fine_block(a.nx, nchains);
+    if (a.ept_hint > 0 && !a.R && nchains >= 64) {
+        const int b = ((a.nx + a.ept_hint - 1) / a.ept_hint + 63) / 64 * 64;
+        if (b <= SLM_MAXB) block = b;
+    }
     const int ept = (a.nx + block - 1) / block;
     const size_t lds = (((size_t)(DBUF ? 2 : 1) * fine_slice_len(a.nx) * sizeof(T) + 15) & ~size_t(15)) +
                        SLM_RED_DOUBLES * sizeof(double);
@@ -75,8 +83,9 @@ hipError_t launch_fine_1d(int nchains, bool f32, const ChainArgs &a, hipStream_t
     // the extra barrier per step (level-0 sweep of the 1D workload: 152 ->
     // 142 us).
     const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
-    const bool dbuf = 2ull * fine_slice_len(a.nx) * (f32 ? 4 : 8) + extra <= (size_t)lds_limit() &&
-                      (f32 || nchains < 512);
+    const bool fits = 2ull * fine_slice_len(a.nx) * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
+    bool dbuf = fits && (f32 || nchains < 512);
+    if (a.dbuf_hint >= 0 && !a.R && nchains >= 64) dbuf = fits && a.dbuf_hint;
     if (f32) return dbuf ? fine_p<float, float, true>(a, nchains, st) : fine_p<float, float, false>(a, nchains, st);
     return dbuf ? fine_p<double, double, true>(a, nchains, st) : fine_p<double, double, false>(a, nchains, st);
 }

@@ -56,6 +56,10 @@ struct slm_plan {
     char *ws = nullptr;
     bool ready = false;
     int elem = 8;                       // sizeof(T)
+    // launch shapes chosen by slm_autotune (they never change the arithmetic):
+    // 2D level-0 tile shape index; 1D level-0 elements per thread and slice
+    // double-buffering for sweeps without a residual (0 = built-in choice)
+    int tile2d = 0, fine_ept = 0, fine_dbuf = -1;
     std::string err;
     WaveField fa, fb;
 };
@@ -86,6 +90,8 @@ struct ChainArgs {
     int adj;                 // 1: adjoint system in reverse time (transposed steps)
     int Nl;                  // level steps; step n of the adjoint uses forward step Nl-1-n
     int fwd;                 // coarse level with the explicit forward-Euler operator (eq. Fp_def)
+    int ept_hint;            // level 0: elements per thread chosen by the autotuner (0: built-in)
+    int dbuf_hint;           // level 0: slice double-buffering chosen by the autotuner (-1: built-in)
 };
 
 // launchers (slm_chain1d.hip / slm_setup.hip / slm_misc.hip)
@@ -99,6 +105,7 @@ hipError_t launch_backtrack_2d(const slm_plan &P, int level, hipStream_t st);
 hipError_t launch_chain_2d(const slm_plan &P, int level, int nchains, const ChainArgs &a, hipStream_t st);
 int chain2d_blocks(long long S);
 int chain2d_tiled(const slm_plan &P, int level, int nchains);
+int chain2d_num_tiles();
 hipError_t launch_sum_partials(const double *partial, int n, double *out, hipStream_t st);
 hipError_t launch_axpy_slices(void *dst, long long dst_stride, const void *src, long long src_stride,
                               int count, int S, int elem, int assign, hipStream_t st);

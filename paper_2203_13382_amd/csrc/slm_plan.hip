@@ -5,8 +5,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
 #include <new>
+#include <sstream>
 
 #include "slm_internal.h"
 
@@ -74,6 +76,8 @@ ChainArgs base_args(const slm_plan &P, int level)
     a.adj = P.adj_mode;
     a.Nl = P.lv[level].N;
     a.fwd = level > 0 && P.d.coarse_op == SLM_COARSE_FWD_EULER ? 1 : 0;
+    a.ept_hint = P.fine_ept;
+    a.dbuf_hint = P.fine_dbuf;
     return a;
 }
 
@@ -493,6 +497,101 @@ int slm_launch_info(const slm_plan *P, int level, int nchains, int *tiled, int *
     if (level < 0 || level >= P->L || nchains < 1) return fail(*P, SLM_EINVAL, "level or chain count out of range");
     if (tiled) *tiled = P->d.dim == 2 ? chain2d_tiled(*P, level, nchains) : 0;
     if (blocks_per_system) *blocks_per_system = P->d.dim == 2 ? P->nb2 : 1;
+    return SLM_OK;
+}
+
+int slm_autotune(slm_plan *P, void *d_ws, size_t bytes, const char *cache_path, void *stream)
+{
+    if (!P) return fail(nullptr, SLM_EINVAL, "plan is NULL");
+    if (!P->ready) return fail(P, SLM_ENOTSETUP, "plan not set up");
+    if (d_ws && (d_ws != (void *)P->ws || bytes < P->ws_bytes))
+        return fail(P, SLM_EINVAL, "d_ws must be the workspace bound at setup (or NULL)");
+    hipStream_t st = (hipStream_t)stream;
+    char key[256];
+    std::snprintf(key, sizeof(key), "plan dim=%d nx=%d nt=%d p=%d r=%d prec=%d m0=%d levels=%d", P->d.dim, P->d.nx,
+                  P->d.nt, P->d.p, P->d.r, P->d.precision, P->lv[0].m, P->L);
+    // a cached choice for this plan shape
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        const std::string pre = std::string(key) + " |";
+        while (std::getline(in, line)) {
+            if (line.compare(0, pre.size(), pre) != 0) continue;
+            int tile = 0, ept = 0, dbuf = -1;
+            if (std::sscanf(line.c_str() + pre.size(), " tile=%d ept=%d dbuf=%d", &tile, &ept, &dbuf) == 3 &&
+                tile >= 0 && tile < chain2d_num_tiles() && (ept == 0 || ept == 1 || ept == 2 || ept == 4 || ept == 8) &&
+                dbuf >= -1 && dbuf <= 1) {
+                P->tile2d = tile;
+                P->fine_ept = ept;
+                P->fine_dbuf = dbuf;
+                return SLM_OK;
+            }
+        }
+    }
+    struct Cand { int tile, ept, dbuf; };
+    std::vector<Cand> cands;
+    if (P->L > 1 && !P->d.adjoint) {
+        if (P->d.dim == 2) {
+            for (int t = 0; t < chain2d_num_tiles(); ++t) cands.push_back({t, 0, -1});
+        } else {
+            const Cand c1[] = {{0, 0, -1}, {0, 4, 0}, {0, 4, 1}, {0, 8, 0}, {0, 8, 1}};
+            for (const Cand &c : c1)
+                if (c.ept == 0 || P->d.nx >= 64 * c.ept) cands.push_back(c);
+        }
+    }
+    if (cands.size() > 1) {
+        // time the level-0 F+C sweep (Sec. 2.2) of every candidate shape on
+        // the plan's own C-point buffers
+        const LevelInfo &L0 = P->lv[0];
+        const int nc0 = P->d.nt / L0.m;
+        HIPCHK(hipMemsetAsync(ws_at(*P, L0.C), 0, ((size_t)nc0 + 1) * P->S * P->elem, st));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(P, SLM_EHIP, "hipEventCreate failed");
+        }
+        float best = 0.0f;
+        Cand bc = cands[0];
+        int rc = SLM_OK;
+        for (const Cand &c : cands) {
+            P->tile2d = c.tile;
+            P->fine_ept = c.ept;
+            P->fine_dbuf = c.dbuf;
+            ChainArgs a = base_args(*P, 0);
+            a.nsteps = L0.m;
+            a.Cin = ws_at(*P, L0.C);
+            a.Cout = ws_at(*P, P->C0b);
+            hipError_t e = chain(*P, 0, nc0, a, st);                 // warm-up
+            for (int r = 0; e == hipSuccess && r < 3; ++r) {
+                if (r == 0) e = hipEventRecord(e0, st);
+                if (e == hipSuccess) e = chain(*P, 0, nc0, a, st);
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(P, SLM_EHIP, std::string("autotune timing: ") + hipGetErrorString(e));
+                break;
+            }
+            if (&c == &cands[0] || ms < best) {
+                best = ms;
+                bc = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        P->tile2d = bc.tile;
+        P->fine_ept = bc.ept;
+        P->fine_dbuf = bc.dbuf;
+        if (rc != SLM_OK) return rc;
+    }
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (!out) return fail(P, SLM_EINVAL, std::string("cannot append to ") + cache_path);
+        out << key << " | tile=" << P->tile2d << " ept=" << P->fine_ept << " dbuf=" << P->fine_dbuf << "\n";
+    }
     return SLM_OK;
 }
 

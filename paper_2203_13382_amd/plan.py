@@ -90,6 +90,19 @@ class Plan:
             sig = self._view(ds.value, dim * Nl * self.S * 8, torch.float64, (dim, Nl, self.S))
         return disp, sig
 
+    def autotune(self, cache_path=None, stream=None):
+        """Pick the level-0 launch shape by timing (slm_autotune); with a
+        cache file the choice is read from / appended to it."""
+        cp = None if cache_path is None else str(cache_path).encode()
+        N.check(N.lib().slm_autotune(self.h, None, 0, cp, _stream(stream)), self.h)
+        return self
+
+    def tile_choice(self):
+        """The 2D level-0 tile shape index in force (slm_launch_info), or
+        None when the level-0 step is not LDS-tiled."""
+        t, _ = self.launch_info(0, max(1, self.N[0] // max(1, self.m[0])))
+        return t - 1 if t > 0 else None
+
     def launch_info(self, level, nchains):
         """(tiled, blocks_per_system) of level ``level``'s step over
         ``nchains`` intervals (slm_launch_info)."""

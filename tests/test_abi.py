@@ -215,3 +215,14 @@ def test_2d_per_block_slots_fit_the_workspace(nx, nt, m):
         assert N.lib().slm_launch_info(h, len(Ns), 1, None, None) == -1
     finally:
         N.lib().slm_plan_destroy(h)
+
+
+def test_autotune_needs_setup():
+    pr = W.Problem(1, 64, 64, 0.05, 3, 3, W.alpha_cfg12())
+    rc, h, _ = _create(pr, W.Solver(m=[4]))
+    assert rc == 0
+    try:
+        assert N.lib().slm_autotune(h, None, 0, None, None) == -5
+        assert N.lib().slm_autotune(None, None, 0, None, None) == -1
+    finally:
+        N.lib().slm_plan_destroy(h)

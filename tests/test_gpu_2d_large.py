@@ -98,7 +98,7 @@ def _rel(a, b):
 def _assert_large_path(plan):
     nc0 = plan.N[0] // plan.m[0]
     tiled, nb = plan.launch_info(0, nc0)
-    assert tiled == 1, "level-0 sweep does not take the LDS-tiled step"
+    assert tiled >= 1, "level-0 sweep does not take the LDS-tiled step"
     assert nb > 1, "batched GMRES runs one block per system"
     assert plan.S > 1024
 
@@ -135,7 +135,7 @@ def test_apply_phi_every_level(name, oracle, torch):
     for l in range(plan.L):
         cnt = plan.N[l] if l > 0 else plan.N[0] // plan.m[0]
         if l == 0:
-            assert plan.launch_info(0, cnt)[0] == 1
+            assert plan.launch_info(0, cnt)[0] >= 1
         n0 = plan.N[l] - cnt
         xin = rng.standard_normal((cnt, pr.S))
         out = plan.apply_phi(l, n0, torch.from_numpy(xin)).cpu().numpy()
