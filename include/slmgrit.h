@@ -200,14 +200,16 @@ int slm_relax(slm_plan *plan, int level, int mode, const void *d_g,
  * loops, harnesses that forbid hipMalloc).  Same arguments, results and
  * kernels as slm_relax; the residual partial sums and the norm live in a
  * static device array of the library (one per GPU, (SLM_NOALLOC_MAX_CHAINS
- * + 32) doubles = 512.25 KiB, held until the process ends) instead of the
+ * + 32) doubles = 128.25 KiB, held until the process ends) instead of the
  * plan's workspace, and the GMRES statistics counters are not updated.  The
  * call allocates nothing.  Limits: 1D plans only (SLM_EUNSUPPORTED
  * otherwise); at most SLM_NOALLOC_MAX_CHAINS intervals on the level
- * (SLM_EINVAL otherwise, nothing launched).  Every call on one GPU shares
+ * (SLM_EINVAL otherwise, nothing launched; a plan has at most 65536 time
+ * steps, the grid.y limit, so this covers every m >= 4 and nt <= 32768
+ * at m = 2).  Every call on one GPU shares
  * that GPU's array: calls that overlap on one GPU (other streams or host
  * threads) race on it and must be serialised by the caller. */
-#define SLM_NOALLOC_MAX_CHAINS 65536
+#define SLM_NOALLOC_MAX_CHAINS 16384
 int slm_relax_noalloc(slm_plan *plan, int level, int mode, const void *d_g, const void *d_c_in, void *d_c_out,
                       void *d_res, void *d_v, double *h_norm, void *stream);
 
@@ -238,7 +240,11 @@ int slm_seed_iterate(slm_plan *plan, uint64_t seed, void *d_u, int layout, void 
  * entry its C-points (every m_0-th slice) are the initial iterate, on exit
  * it holds the approximation of every time point.  d_u0 is u_0.  The
  * residual history rho_k is written to h_hist[k] for k < hist_cap.  Returns
- * the stats status (>= 0) or an error (< 0). */
+ * the stats status (>= 0) or an error (< 0).  A run stopped by max_iter
+ * (SLM_NOT_CONVERGED) completes its last cycle's coarse-grid correction, so
+ * the iterate it leaves in d_u is the one the next cycle would start from:
+ * calling slm_solve again on it continues the iteration exactly (resume;
+ * the relative tolerance then refers to the new call's first residual). */
 int slm_solve(slm_plan *plan, const void *d_u0, void *d_u, slm_stats *stats,
               double *h_hist, int hist_cap, void *stream);
 

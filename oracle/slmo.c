@@ -916,7 +916,8 @@ static void cycle_from(slmo_ctx *c, int l)
  * grows by many orders of magnitude and still converges in the printed
  * number of cycles (rounding added at the peak is damped like any other
  * error of the iterate);
- * NOT_CONVERGED once k reaches max_iter. */
+ * NOT_CONVERGED once k reaches max_iter, after that cycle's coarse-grid
+ * correction (the returned iterate is where cycle k+1 would start). */
 int slmo_mgrit(slmo_ctx *c, const double *u0, double *u, double *hist, int hist_cap,
                slmo_stats *st)
 {
@@ -947,9 +948,12 @@ int slmo_mgrit(slmo_ctx *c, const double *u0, double *u, double *hist, int hist_
             double thr = c->sv.tol_mode == SLMO_TOL_REL ? c->sv.tol * rho0 : c->sv.tol;
             if (rho < thr || rho == 0.0) { s.status = SLMO_CONVERGED; break; }
             if (!isfinite(rho)) { s.status = SLMO_DIVERGED; break; }
-            if (k >= c->sv.max_iter) { s.status = SLMO_NOT_CONVERGED; break; }
             coarse_correct(c, 0);
             f_relax(c, 0);
+            /* Reading: a run cut off at max_iter still completes the cycle's
+             * coarse-grid correction, so the iterate it leaves is the one the
+             * next cycle starts from and a second call resumes exactly. */
+            if (k >= c->sv.max_iter) { s.status = SLMO_NOT_CONVERGED; break; }
         }
         s.rho0 = rho0;
     }

@@ -224,13 +224,18 @@ int solve_core(slm_plan *P, const void *d_u0, void *d_u, void *d_c, slm_stats *s
             s.iterations = k + 1;
             s.rho_final = rho;
             const double thr = P->d.tol_mode == SLM_TOL_REL ? P->d.tol * rho0 : P->d.tol;
-            bool stop = true;
+            bool stop = true, last = false;
             if (rho < thr || rho == 0.0) s.status = SLM_OK;
             else if (!std::isfinite(rho)) s.status = SLM_DIVERGED;
             else if (P->d.precision == SLM_FP32_BULK && k > 0 && (stag = rho > 0.95 * prev ? stag + 1 : 0) >= 3)
                 s.status = SLM_STAGNATED;
-            else if (k >= P->d.max_iter) s.status = SLM_NOT_CONVERGED;
-            else stop = false;
+            else if (k >= P->d.max_iter) {
+                // cut off: still apply this cycle's correction, so the iterate
+                // left is where the next cycle starts (a later call resumes)
+                s.status = SLM_NOT_CONVERGED;
+                stop = false;
+                last = true;
+            } else stop = false;
             prev = rho;
             if (stop) {
                 Ca = Cc;
@@ -240,6 +245,7 @@ int solve_core(slm_plan *P, const void *d_u0, void *d_u, void *d_c, slm_stats *s
             if (rc) return rc;
             HIPCHK(launch_axpy_slices(Cc + sl, S, ws_at(*P, P->lv[1].V) + sl, S, nc0, S, P->elem, 0, st));
             if (fcf) std::swap(Ca, Cb);     // the corrected C-values become the next cycle's start
+            if (last) break;
         }
         s.rho0 = rho0;
         if (u) {
@@ -708,7 +714,8 @@ int slm_relax_noalloc(slm_plan *P, int level, int mode, const void *d_g, const v
     const LevelInfo &L = P->lv[level];
     const int m = L.m, nc = L.N / m;
     if (nc > SLM_NOALLOC_MAX_CHAINS)
-        return fail(P, SLM_EINVAL, "slm_relax_noalloc: more than SLM_NOALLOC_MAX_CHAINS (65536) intervals on this level");
+        return fail(P, SLM_EINVAL, "slm_relax_noalloc: more than SLM_NOALLOC_MAX_CHAINS (" +
+                                   std::to_string(SLM_NOALLOC_MAX_CHAINS) + ") intervals on this level");
     double *scr = nullptr;
     HIPCHK(scratch_on_current_device(&scr));
     ChainArgs a = base_args(*P, level);

@@ -195,6 +195,13 @@ def test_mgrit_solve(name, oracle, torch, built):
     assert torch.equal(u, u2) and np.array_equal(hist, hist2)
 
 
+# FP32-bulk error bounds against the FP64 oracle (stepping, MGRIT to a
+# relative 1e-6): about three times the errors measured on MI355X.
+# Measured: cfg1 3.7e-7 / 4.8e-6, cfg2_small 5.8e-6 / 1.3e-5, ragged_p5
+# 2.8e-6 / 5.0e-6.
+FP32_BOUND = {"cfg1": (1.2e-6, 1.5e-5), "cfg2_small": (1.8e-5, 4e-5), "ragged_p5": (9e-6, 1.5e-5)}
+
+
 @pytest.mark.parametrize("name", ["cfg1", "cfg2_small", "ragged_p5"])
 def test_fp32_bulk(name, oracle, torch, built):
     """FP32 bulk (FP64 tracing, sigma, inner products and norms): stepping
@@ -209,7 +216,9 @@ def test_fp32_bulk(name, oracle, torch, built):
     u0 = I.initial_condition(pr, 0)
     useq = oracle.seq_fine(pr, u0)
     u = plan.step(torch.from_numpy(u0)).cpu().numpy()
-    assert _rel(u, useq) < 2e-7 * pr.nt
+    e_step = _rel(u, useq)
+    print(f"{name} fp32 stepping: rel. error {e_step:.2e}")
+    assert e_step < FP32_BOUND[name][0]
     if plan.L > 1:
         ui = I.initial_iterate(pr.nt, pr.S, plan.m[0], 1).astype(np.float32)
         uu = torch.from_numpy(ui).cuda()
@@ -219,4 +228,19 @@ def test_fp32_bulk(name, oracle, torch, built):
         p32 = Plan(pr, sv32, "fp32").setup()
         st, hist = p32.solve(torch.from_numpy(u0.astype(np.float32)), uu)
         assert st["status"] in ("converged", "stagnated")
-        assert _rel(uu.cpu().numpy(), useq) < 2e-7 * pr.nt + 1e-5
+        e_mg = _rel(uu.cpu().numpy(), useq)
+        print(f"{name} fp32 MGRIT to rel. 1e-6: rel. error {e_mg:.2e}")
+        assert e_mg < FP32_BOUND[name][1]
+
+
+def test_setup_refuses_nt_above_grid_y(torch, built):
+    # launches put time steps on grid.y: setup refuses more steps than the
+    # device reports for it (65536 on MI355X), before launching anything
+    from paper_2203_13382_amd import Plan
+    from paper_2203_13382_amd._native import NativeError
+    pr = W.Problem(1, 8, 65537, 0.01, 1, 1, [W.term(1.0)])
+    with pytest.raises(NativeError, match="grid.y"):
+        Plan(pr, W.Solver(m=[2], max_levels=2)).setup()
+    pr = W.Problem(1, 8, 65536, 0.01, 1, 1, [W.term(1.0)])
+    plan = Plan(pr, W.Solver(m=[2], max_levels=2)).setup()
+    assert plan.N[0] == 65536

@@ -170,3 +170,23 @@ def test_thread_count_does_not_change_results(oracle, dim):
     assert np.array_equal(u1, u4) and np.array_equal(h1, h4)
     assert np.array_equal(d1, d4) and np.array_equal(g1, g4)
     assert s1 == s4
+
+
+@pytest.mark.parametrize("relax", ["FCF", "F"])
+def test_resume_is_bitwise_continuation(oracle, relax):
+    """A run cut off at max_iter leaves the iterate the next cycle starts
+    from, so k cycles, then j more from that iterate, equal k + j cycles
+    bit for bit (iterate and residual history)."""
+    import dataclasses
+    pr = _prob(48, 192, 1.3, 3)
+    sv = W.Solver(m=[4], coarsest_max_points=2, relax=relax, tol=0.0, tol_mode="abs", gmres_rtol=1e-2)
+    u0 = I.initial_condition(pr, 0)
+    ui = oracle.seeded_iterate(2, pr.nt, pr.S, 4)
+    ua, sa, ha = oracle.Context(pr, dataclasses.replace(sv, max_iter=6)).mgrit(u0, ui)
+    u1, s1, h1 = oracle.Context(pr, dataclasses.replace(sv, max_iter=2)).mgrit(u0, ui)
+    u2, s2, h2 = oracle.Context(pr, dataclasses.replace(sv, max_iter=3)).mgrit(u0, u1)
+    assert sa["status"] == s1["status"] == s2["status"] == "not_converged"
+    assert sa["iterations"] == 7 and s1["iterations"] == 3 and s2["iterations"] == 4
+    assert np.array_equal(ua, u2)
+    assert np.array_equal(ha[3:], h2) and np.array_equal(ha[:3], h1)
+    assert sa["gmres_iters"] == s1["gmres_iters"] + s2["gmres_iters"]

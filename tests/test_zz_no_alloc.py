@@ -69,13 +69,13 @@ def test_noalloc_limits(torch):
     lib = N.lib()
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     # more intervals than the static scratch holds: an error, nothing launched
-    pr = W.Problem(1, 8, 2 * 65537, 0.01, 1, 1, [W.term(1.0)])
+    pr = W.Problem(1, 8, 2 * 16385, 0.01, 1, 1, [W.term(1.0)])
     plan = _plan(pr, W.Solver(m=[2], max_levels=2))
-    assert plan.N[0] // plan.m[0] == 65537
-    res = torch.zeros(65538, 8, dtype=torch.float64, device="cuda")
-    cin = torch.zeros(65538, 8, dtype=torch.float64, device="cuda")
+    assert plan.N[0] // plan.m[0] == 16385
+    res = torch.zeros(16386, 8, dtype=torch.float64, device="cuda")
+    cin = torch.zeros(16386, 8, dtype=torch.float64, device="cuda")
     rc = lib.slm_relax_noalloc(plan.h, 0, N.SWEEP["RES"], None, _ptr(cin), None, _ptr(res), None, None, st)
-    assert rc == -1 and b"65536" in lib.slm_last_error(plan.h)
+    assert rc == -1 and b"16384" in lib.slm_last_error(plan.h)
     # 2D plans are not supported by the allocation-free variant
     a, b = W.field_cfg3()
     p2 = _plan(W.Problem(2, 16, 16, 0.1, 1, 1, a, b), W.Solver(m=[4], max_levels=2))
