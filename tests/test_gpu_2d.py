@@ -173,13 +173,21 @@ def test_mgrit_solve(name, oracle, torch):
     assert torch.equal(u, u2) and np.array_equal(hist, hist2)
 
 
+# FP32-bulk error bounds against the FP64 oracle (stepping, MGRIT to a
+# relative 1e-6): about three times the errors measured on MI355X.
+# Measured: cfg3_field_p5 7.6e-7 / 7.6e-7, cfg5_field_p3 2.7e-7 / 2.7e-7.
+FP32_BOUND = {"cfg3_field_p5": (2.5e-6, 2.5e-6), "cfg5_field_p3": (1e-6, 1e-6)}
+
+
 @pytest.mark.parametrize("name", ["cfg3_field_p5", "cfg5_field_p3"])
 def test_fp32_bulk(name, oracle, torch):
     pr, sv, plan, ctx = _setup(name, oracle, "fp32")
     u0 = I.initial_condition(pr, 0)
     useq = oracle.seq_fine(pr, u0)
     u = plan.step(torch.from_numpy(u0)).cpu().numpy()
-    assert _rel(u, useq) < 2e-7 * pr.nt
+    e_step = _rel(u, useq)
+    print(f"{name} fp32 stepping: rel. error {e_step:.2e}")
+    assert e_step < FP32_BOUND[name][0]
     import dataclasses
     from paper_2203_13382_amd import Plan
     p32 = Plan(pr, dataclasses.replace(sv, tol=1e-6), "fp32").setup()
@@ -187,4 +195,6 @@ def test_fp32_bulk(name, oracle, torch):
     uu = torch.from_numpy(ui).cuda()
     st, hist = p32.solve(torch.from_numpy(u0.astype(np.float32)), uu)
     assert st["status"] in ("converged", "stagnated")
-    assert _rel(uu.cpu().numpy(), useq) < 2e-7 * pr.nt + 1e-5
+    e_mg = _rel(uu.cpu().numpy(), useq)
+    print(f"{name} fp32 MGRIT to rel. 1e-6: rel. error {e_mg:.2e}")
+    assert e_mg < FP32_BOUND[name][1]

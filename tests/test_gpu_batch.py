@@ -155,6 +155,13 @@ def test_batch_tune_and_cache(torch, tmp_path):
         assert np.array_equal(h1[i], h0[i]), i
 
 
+# FP32-bulk error bounds against the FP64 oracle: about three times the
+# largest error measured on MI355X (3.4e-6 over the small batch, 2.6e-5
+# over the checked problems of the full-size batch).
+FP32_BATCH_BOUND = 1e-5
+FP32_FULL_BATCH_BOUND = 8e-5
+
+
 def test_batch_fp32_bulk(oracle, torch):
     import dataclasses
     from paper_2203_13382_amd import Batch
@@ -163,10 +170,14 @@ def test_batch_fp32_bulk(oracle, torch):
     u0s, uis = _inputs(probs, np.float32)
     us = [torch.from_numpy(u).cuda() for u in uis]
     st, _ = b.solve(u0s, us)
+    worst = 0.0
     for i, (pr, sv) in enumerate(probs):
         assert st[i]["status"] in ("converged", "stagnated"), (i, st[i])
         useq = oracle.seq_fine(pr, u0s[i].astype(np.float64))
-        assert _rel(us[i].cpu().numpy(), useq) < 2e-7 * pr.nt + 1e-5, i
+        e = _rel(us[i].cpu().numpy(), useq)
+        worst = max(worst, e)
+        assert e < FP32_BATCH_BOUND, (i, e)
+    print(f"batch fp32: worst rel. error vs the FP64 oracle {worst:.2e}")
 
 
 def test_batch_full_size_workload(oracle, torch):
@@ -190,7 +201,9 @@ def test_batch_full_size_workload(oracle, torch):
     for i in cheap:
         pr = probs[i][0]
         useq = oracle.seq_fine(pr, u0s[i].astype(np.float64))
-        assert _rel(us[i].cpu().numpy(), useq) < 2e-7 * pr.nt + 1e-5, i
+        e = _rel(us[i].cpu().numpy(), useq)
+        print(f"full batch problem {i} (nx {pr.nx}, nt {pr.nt}, p {pr.p}): fp32 rel. error {e:.2e}")
+        assert e < FP32_FULL_BATCH_BOUND, (i, e)
     from paper_2203_13382_amd import Plan
     rng = np.random.default_rng(5)
     for i in rng.choice([k for k in range(len(probs)) if k not in cheap], 2, replace=False):

@@ -92,5 +92,5 @@ def test_cfg2_fp32_bulk_error(torch):
     seq = np.array([s[3] for s in g["samples"]])
     err = np.abs(got - seq).max() / g["max_abs_seq"]
     print(f"cfg2 FP32-bulk max rel error vs FP64 oracle at 256 samples: {err:.3e}")
-    # FP32 rounding of each SL step accumulates at most linearly in nt
-    assert err < 2e-7 * 16384
+    # measured 3.4e-5 (MGRIT to rel. 1e-6 from FP32 slices and weights)
+    assert err < 1e-4
