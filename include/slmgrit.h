@@ -39,6 +39,12 @@
 extern "C" {
 #endif
 
+/* Largest nt a plan takes: launches put time steps, coarse steps or
+ * intervals on grid.y, whose limit HIP reports as 65536 on gfx950.
+ * slm_plan_create refuses more with SLM_EUNSUPPORTED, and slm_plan_setup
+ * also checks the current device's reported limit. */
+#define SLM_MAX_NT 65536
+
 /* One term of a wave-speed field (Sec. 2.1 requires alpha(x,t) computable
  * anywhere): coef*cos(kx*pi*x+px)*cos(ky*pi*y+py)*cos(kt*pi*t+pt).  A field
  * is a sum of at most SLM_MAX_TERMS terms. */
@@ -75,7 +81,7 @@ enum {
 typedef struct {
     int dim;                   /* 1 or 2 */
     int nx;                    /* nodes per axis, >= 8 (1D: <= 8192, 2D: <= 4096) */
-    int nt;                    /* fine time steps, >= 1 */
+    int nt;                    /* fine time steps, 1..SLM_MAX_NT */
     double dt;                 /* fine time step (> 0) */
     int p;                     /* interpolation degree 1..5 (MGRIT: odd p only) */
     int r;                     /* ERK order 1..5 of the departure trace */

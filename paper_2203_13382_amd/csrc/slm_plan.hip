@@ -308,6 +308,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
     if (d->nx < 8 || (d->dim == 1 && d->nx > 8192) || (d->dim == 2 && d->nx > 4096))
         return fail(nullptr, SLM_EUNSUPPORTED, "nx out of range (1D: 8..8192, 2D: 8..4096)");
     if (d->nt < 1 || !(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(nullptr, SLM_EINVAL, "nt >= 1 and dt > 0 required");
+    if (d->nt > SLM_MAX_NT) return fail(nullptr, SLM_EUNSUPPORTED, "nt above SLM_MAX_NT (65536, the grid.y limit)");
     if (d->p < 1 || d->p > 5) return fail(nullptr, SLM_EUNSUPPORTED, "p must be 1..5");
     if (d->r < 1 || d->r > 5) return fail(nullptr, SLM_EUNSUPPORTED, "r must be 1..5");
     if (d->n_alpha < 1 || d->n_alpha > SLM_MAX_TERMS || !d->alpha) return fail(nullptr, SLM_EINVAL, "alpha needs 1..8 terms");

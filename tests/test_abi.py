@@ -72,6 +72,7 @@ def test_hierarchy_matches_oracle(oracle, nt, kw):
 @pytest.mark.parametrize("change,code", [
     (dict(dim=3), -2), (dict(nx=4), -2), (dict(nx=9000), -2), (dict(p=6), -2), (dict(r=0), -2),
     (dict(dt=0.0), -1), (dict(nt=0), -1), (dict(alpha=[]), -1),
+    (dict(nt=65537), -2),                 # above the grid.y limit (SLM_MAX_NT)
     (dict(p=2), -2),                      # MGRIT needs odd p
 ])
 def test_descriptor_validation(change, code):
