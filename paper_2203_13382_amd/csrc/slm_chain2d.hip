@@ -24,6 +24,7 @@
 // right-hand side is the incoming slice, the matvec the transposed one, and
 // the transposed interpolation follows the solve.
 #include <cmath>
+#include <type_traits>
 
 #include "slm_internal.h"
 
@@ -227,17 +228,12 @@ __global__ void __launch_bounds__(TPB) g2_norm0(const T *__restrict__ b, long lo
     write_parts<1>(v, red, part, c);
 }
 
-// Fixed-order reduction of the per-block partials of every system: one
-// workgroup per system sums its nb blocks' slots q < nv (each thread a
-// strided subset, then a deterministic workgroup tree) into out[c][q].
-// Systems already converged are skipped when gs is given.
-__global__ void __launch_bounds__(TPB) g2_sum(const double *__restrict__ part, int nb, int nv, const Gs2 *gs,
-                                              double *__restrict__ out)
+// Fixed-order reduction of the per-block partials of system c: one
+// workgroup sums the nb blocks' slots q < nv (each thread a strided subset,
+// then a deterministic workgroup tree); every thread receives the totals.
+__device__ __forceinline__ void sum_parts(const double *part, int nb, int nv, int c, double (&v)[SLM_KMAX + 1],
+                                          double *red, int buf)
 {
-    __shared__ double red[SLM_RED_DOUBLES];
-    const int c = blockIdx.x;
-    if (gs && gs[c].done) return;
-    double v[SLM_KMAX + 1];
 #pragma unroll
     for (int q = 0; q <= SLM_KMAX; ++q) v[q] = 0.0;
     for (int b = threadIdx.x; b < nb; b += TPB) {
@@ -246,7 +242,19 @@ __global__ void __launch_bounds__(TPB) g2_sum(const double *__restrict__ part, i
         for (int q = 0; q <= SLM_KMAX; ++q)
             if (q < nv) v[q] += pp[q];
     }
-    block_sum_rs<SLM_KMAX + 1>(v, red, 0);
+    block_sum_rs<SLM_KMAX + 1>(v, red, buf);
+}
+
+// Totals of the per-block partials, one workgroup per system, into
+// out[c][q] (q < nv).  Systems already converged are skipped when gs is given.
+__global__ void __launch_bounds__(TPB) g2_sum(const double *__restrict__ part, int nb, int nv, const Gs2 *gs,
+                                              double *__restrict__ out)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.x;
+    if (gs && gs[c].done) return;
+    double v[SLM_KMAX + 1];
+    sum_parts(part, nb, nv, c, v, red, 0);
     if (threadIdx.x < nv) out[(long long)c * NPART + threadIdx.x] = v[threadIdx.x];
 }
 
@@ -272,24 +280,34 @@ __global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long lo
         V0[id] = T(double(b[c * S + id]) * inv);
 }
 
-// w = V_j - sx .* (D_x V_j) - sy .* (D_y V_j), or for the adjoint system
-// (transpose) w = V_j - D_x (sx .* V_j) - D_y (sy .* V_j); partials of
-// V_i . w, i <= j.  1D slices have no y term.  The sigma of step n (or of
-// the mirrored step Nl-1-n when rev) is used.
-template <typename T, int P>
-__global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__restrict__ W, long long S, int nx,
-                                                  const double *__restrict__ sig, long long plane, long long n_first,
-                                                  int stride, int j, const Gs2 *gs, double *part, int dim,
-                                                  int transpose, int rev, int Nl)
+// Arnoldi step j of every system c (blockIdx.y):
+//   v = V_0 (j = 0) or w_{j-1} / hn_{j-1}, the previous step's vector
+//       normalised here (and stored as V_j) rather than in a launch of its own;
+//   w = v - sx .* (D_x v) - sy .* (D_y v), or for the adjoint system
+//       (transpose) w = v - D_x (sx .* v) - D_y (sy .* v);
+// then the partials of the projections V_i . w (i <= j).  1D slices have
+// no y term.  The sigma of step n (or of Nl-1-n when rev) is read in TS: FP64,
+// or its float copy for FP32 bulk.
+template <typename T, typename TS, int P>
+__global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__restrict__ Wsrc, T *__restrict__ Wdst,
+                                                  long long S, int nx, const TS *__restrict__ sig, long long plane,
+                                                  long long n_first, int stride, int j, const Gs2 *gs, double *part,
+                                                  int dim, int transpose, int rev, int Nl)
 {
     __shared__ double red[SLM_RED_DOUBLES];
     const int c = blockIdx.y;
     if (gs[c].done) return;
     const long long n0 = n_first + (long long)c * stride;
     const long long n = rev ? Nl - 1 - n0 : n0;
-    const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
-    const T *vj = Vc + (long long)j * S;
-    const double *sx = sig + n * S, *sy = sig + plane + n * S;
+    T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
+    const T *src = j == 0 ? Vc : Wsrc + (long long)c * S;
+    double inv = 1.0;
+    if (j > 0) {
+        const double hn = gs[c].hn[j - 1];
+        inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+    auto ld = [&](long long ix) { return T(double(src[ix]) * inv); };   // V_j at node ix
+    const TS *sx = sig + n * S, *sy = sig + plane + n * S;
     constexpr int q = DTaps<P>::q;
     double h[SLM_KMAX + 1];
 #pragma unroll
@@ -305,74 +323,35 @@ __global__ void __launch_bounds__(TPB) g2_matvec(const T *__restrict__ V, T *__r
             ii += ii < 0 ? nx : 0;
             ii -= ii >= nx ? nx : 0;
             const long long ix = (long long)jr * nx + ii;
-            dxv += DTaps<P>::t[t + q] * (transpose ? sx[ix] * double(vj[ix]) : double(vj[ix]));
+            dxv += DTaps<P>::t[t + q] * (transpose ? double(sx[ix]) * double(ld(ix)) : double(ld(ix)));
             if (dim == 2) {
                 int jj = jr + t;
                 jj += jj < 0 ? nx : 0;
                 jj -= jj >= nx ? nx : 0;
                 const long long iy = (long long)jj * nx + i;
-                dyv += DTaps<P>::t[t + q] * (transpose ? sy[iy] * double(vj[iy]) : double(vj[iy]));
+                dyv += DTaps<P>::t[t + q] * (transpose ? double(sy[iy]) * double(ld(iy)) : double(ld(iy)));
             }
         }
-        const double yterm = dim == 2 ? (transpose ? dyv : sy[id] * dyv) : 0.0;
-        const T w = T(double(vj[id]) - (transpose ? dxv : sx[id] * dxv) - yterm);
-        W[c * S + id] = w;
+        const T vj = ld(id);
+        if (j > 0) Vc[(long long)j * S + id] = vj;
+        const double yterm = dim == 2 ? (transpose ? dyv : double(sy[id]) * dyv) : 0.0;
+        const T w = T(double(vj) - (transpose ? dxv : double(sx[id]) * dxv) - yterm);
+        Wdst[c * S + id] = w;
 #pragma unroll
         for (int k = 0; k <= SLM_KMAX; ++k)
-            if (k <= j) h[k] += double(Vc[(long long)k * S + id]) * double(w);
+            if (k <= j) h[k] += double(k == j ? vj : Vc[(long long)k * S + id]) * double(w);
     }
     block_sum_rs<SLM_KMAX + 1>(h, red, 0);
     if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
-// w -= sum_i h_i V_i with the reduced h (i <= j); then partials of V_i . w
-// (i <= j) when `dots`, or of w . w otherwise.
-template <typename T>
-__global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__restrict__ W, long long S, int j,
-                                                  const Gs2 *gs, const double *__restrict__ hin, double *part_out,
-                                                  int dots)
+// Givens recurrence of system g after Arnoldi step j: h = the Gram-Schmidt
+// coefficients, hn the norm of the orthogonalised vector (Sec. 3.3 GMRES,
+// same arithmetic order as the 1D kernel).  One thread.
+__device__ __forceinline__ void givens_step(Gs2 &g, int j, const double *h1, double hn, double rtol, int kmax)
 {
-    __shared__ double red[SLM_RED_DOUBLES];
-    __shared__ double hs[SLM_KMAX + 1];
-    const int c = blockIdx.y;
-    if (gs[c].done) return;
-    const int nb = gridDim.x;
-    if (threadIdx.x <= j) hs[threadIdx.x] = hin[(long long)c * NPART + threadIdx.x];
-    __syncthreads();
-    const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
-    double h[SLM_KMAX + 1];
-#pragma unroll
-    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
-    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
-        double t = double(W[c * S + id]);
-        for (int k = 0; k <= j; ++k) t -= hs[k] * double(Vc[(long long)k * S + id]);
-        const T w = T(t);
-        W[c * S + id] = w;
-        if (dots) {
-#pragma unroll
-            for (int k = 0; k <= SLM_KMAX; ++k)
-                if (k <= j) h[k] += double(Vc[(long long)k * S + id]) * double(w);
-        } else {
-            h[0] += double(w) * double(w);
-        }
-    }
-    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
-    const int nv = dots ? j + 1 : 1;
-    if (threadIdx.x < nv) part_out[((long long)c * nb + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
-}
-
-// Givens recurrence, one thread per system: h = the Gram-Schmidt
-// coefficients, hn from the reduced norm (Sec. 3.3 GMRES, same arithmetic
-// order as the 1D kernel).
-__global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *h1, const double *nn, double rtol, int kmax)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nsys) return;
-    Gs2 &g = gs[c];
-    if (g.done) return;
     double hc[SLM_KMAX + 1];
-    for (int i = 0; i <= j; ++i) hc[i] = h1[(long long)c * NPART + i];
-    const double hn = sqrt(nn[(long long)c * NPART]);
+    for (int i = 0; i <= j; ++i) hc[i] = h1[i];
     for (int i = 0; i < j; ++i) {
         const double t0 = g.cs[i] * hc[i] + g.sn[i] * hc[i + 1];
         const double t1 = -g.sn[i] * hc[i] + g.cs[i] * hc[i + 1];
@@ -393,17 +372,45 @@ __global__ void g2_givens(Gs2 *gs, int nsys, int j, const double *h1, const doub
     if (hn == 0.0 || fabs(ss * gj) <= rtol * g.beta || j + 1 >= kmax) g.done = 1;
 }
 
-// V_{j+1} = w / hn for systems still iterating.
+// w -= sum_i h_i V_i with the reduced h (i <= j), then the partials of w . w.
 template <typename T>
-__global__ void __launch_bounds__(TPB) g2_normalize(T *V, const T *__restrict__ W, long long S, int j, const Gs2 *gs)
+__global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__restrict__ W, long long S, int j,
+                                                  const Gs2 *gs, const double *__restrict__ hin, double *part)
 {
+    __shared__ double red[SLM_RED_DOUBLES];
+    __shared__ double hs[SLM_KMAX + 1];
     const int c = blockIdx.y;
     if (gs[c].done) return;
-    const double hn = gs[c].hn[j];
-    const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
-    T *vn = V + ((long long)c * (SLM_KMAX + 1) + j + 1) * S;
-    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB)
-        vn[id] = T(double(W[c * S + id]) * inv);
+    const int nb = gridDim.x;
+    if (threadIdx.x <= j) hs[threadIdx.x] = hin[(long long)c * NPART + threadIdx.x];
+    __syncthreads();
+    const T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
+    double h[SLM_KMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
+    for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
+        double t = double(W[c * S + id]);
+        for (int k = 0; k <= j; ++k) t -= hs[k] * double(Vc[(long long)k * S + id]);
+        const T w = T(t);
+        W[c * S + id] = w;
+        h[0] += double(w) * double(w);
+    }
+    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
+    if (threadIdx.x == 0) part[((long long)c * nb + blockIdx.x) * NPART] = h[0];
+}
+
+// ||w|| of every system from the update's partials (one workgroup per
+// system, fixed order), then the Givens step, which may end the system's
+// iteration.  h1: the reduced projections.
+__global__ void __launch_bounds__(TPB) g2_norm_givens(const double *__restrict__ part, int nb, Gs2 *gs, int j,
+                                                      const double *__restrict__ h1, double rtol, int kmax)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.x;
+    if (gs[c].done) return;
+    double v[SLM_KMAX + 1];
+    sum_parts(part, nb, 1, c, v, red, 0);
+    if (threadIdx.x == 0) givens_step(gs[c], j, h1 + (long long)c * NPART, sqrt(v[0]), rtol, kmax);
 }
 
 // y = V z (back substitution per block), then dst[c] = y (+ G[n+1]), Vout.
@@ -581,13 +588,13 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, const T *V, T *W, long long S, int nx, const double *sig,
-                         long long plane, long long n_first, int stride, int j, const Gs2 *gs, double *part, int dim,
-                         int transpose, int rev, int Nl)
+template <typename T, typename TS>
+hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, T *V, const T *Wsrc, T *Wdst, long long S, int nx,
+                         const TS *sig, long long plane, long long n_first, int stride, int j, const Gs2 *gs,
+                         double *part, int dim, int transpose, int rev, int Nl)
 {
-#define MV(PP) hipLaunchKernelGGL((g2_matvec<T, PP>), grid, dim3(TPB), 0, st, V, W, S, nx, sig, plane, n_first, stride, \
-                                  j, gs, part, dim, transpose, rev, Nl)
+#define MV(PP) hipLaunchKernelGGL((g2_matvec<T, TS, PP>), grid, dim3(TPB), 0, st, V, Wsrc, Wdst, S, nx, sig, plane, \
+                                  n_first, stride, j, gs, part, dim, transpose, rev, Nl)
     switch (p) {
     case 1: MV(1); break;
     case 3: MV(3); break;
@@ -685,28 +692,39 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                 continue;
             }
             T *V = (T *)ws_at(P, P.g2v);
-            T *W = (T *)ws_at(P, P.g2w);
+            T *Wb2[2] = {(T *)ws_at(P, P.g2w), (T *)ws_at(P, P.g2w) + (long long)P.capg * S};
             Gs2 *gs = (Gs2 *)ws_at(P, P.g2s);
             double *pa = (double *)ws_at(P, P.g2p), *pb = pa + (long long)P.capg * nb * NPART;
             double *pc = pb + (long long)P.capg * nb * NPART;
             double *r1 = pc + (long long)P.capg * nb * NPART, *r2 = r1 + (long long)P.capg * NPART;
             double *r3 = r2 + (long long)P.capg * NPART;
-            const double *sig = (const double *)ws_at(P, L.sigma);
             hipLaunchKernelGGL(g2_norm0<T>, grid, dim3(TPB), 0, st, rhs, S, pa);
             hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, 1, (const Gs2 *)nullptr, r3);
             hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, rhs, S, r3, V, gs, a.kmax);
+            // Arnoldi step j: the matvec (normalising w_{j-1} on the fly) with
+            // the partial projections, their totals, classical Gram-Schmidt
+            // w -= V h with the partials of ||w||^2, then ||w|| and the Givens
+            // step.  w alternates between two buffers so the matvec's stencil
+            // reads w_{j-1} while it writes w_j.
             for (int j = 0; j < a.kmax; ++j) {
-                if ((e = launch_matvec<T>(P.d.p, grid, st, V, W, S, nx, sig, plane, n_first0 + k, a.stride_chain, j, gs,
-                                          pa, P.d.dim, a.adj, a.adj, L.N)) != hipSuccess)
-                    return e;
-                // classical Gram-Schmidt: w -= V h with the projections of the
-                // matvec, then the partials of ||w||^2
+                T *Wsrc = Wb2[(j + 1) & 1], *Wdst = Wb2[j & 1];
+                bool done = false;
+                if constexpr (std::is_same<T, float>::value) {
+                    if (L.sigma32) {                // FP32 bulk: sigma rounded to float
+                        e = launch_matvec<T, float>(P.d.p, grid, st, V, Wsrc, Wdst, S, nx,
+                                                    (const float *)ws_at(P, L.sigma32), plane, n_first0 + k,
+                                                    a.stride_chain, j, gs, pa, P.d.dim, a.adj, a.adj, L.N);
+                        done = true;
+                    }
+                }
+                if (!done)
+                    e = launch_matvec<T, double>(P.d.p, grid, st, V, Wsrc, Wdst, S, nx,
+                                                 (const double *)ws_at(P, L.sigma), plane, n_first0 + k,
+                                                 a.stride_chain, j, gs, pa, P.d.dim, a.adj, a.adj, L.N);
+                if (e != hipSuccess) return e;
                 hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, j + 1, gs, r1);
-                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs, r1, pc, 0);
-                hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pc, nb, 1, gs, r3);
-                hipLaunchKernelGGL(g2_givens, dim3((nch + 63) / 64), dim3(64), 0, st, gs, nch, j, r1, r3,
-                                   a.rtol, a.kmax);
-                hipLaunchKernelGGL(g2_normalize<T>, grid, dim3(TPB), 0, st, V, W, S, j, gs);
+                hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, Wdst, S, j, gs, r1, pc);
+                hipLaunchKernelGGL(g2_norm_givens, dim3(nch), dim3(TPB), 0, st, pc, nb, gs, j, r1, a.rtol, a.kmax);
             }
             if (a.adj) {
                 // y = (B^T)^{-1} rhs, then the transposed interpolation S_l^T y

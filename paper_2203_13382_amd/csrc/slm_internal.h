@@ -14,6 +14,7 @@ struct LevelInfo {
     size_t disp = 0;        // [dim][N][S] displacements (double; level 0 of bulk: float)
     size_t disp64 = 0;      // level 0 of an FP32-bulk plan: FP64 copy used by setup
     size_t sigma = 0;       // [dim][N][S] double, l >= 1
+    size_t sigma32 = 0;     // 2D FP32-bulk plans: [dim][N][S] float copy of sigma for the GMRES matvec
     size_t V = 0;           // [(N+1)][S] T, l >= 1: iterate
     size_t G = 0;           // [(N+1)][S] T, l >= 1: right-hand side
     size_t C = 0;           // [(N/m+1)][S] T: C-point buffer (not on the coarsest level)
@@ -124,6 +125,7 @@ hipError_t launch_grad(const slm_plan &P, int nch, const double *U, long long u_
                        long long lam_stride, long long n_first, int stride, double *gacc, hipStream_t st);
 hipError_t launch_grad_reduce(const slm_plan &P, int nchains, double *out, hipStream_t st);
 hipError_t launch_fill0(double *p, long long n, hipStream_t st);
+hipError_t launch_narrow(const double *src, float *dst, long long n, hipStream_t st);
 
 // message returned by slm_last_error(NULL) (slm_plan.hip)
 void slm_set_error(const std::string &msg);

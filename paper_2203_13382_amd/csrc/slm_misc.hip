@@ -53,7 +53,23 @@ __global__ void seed_kernel(T *__restrict__ u, long long ls, int c0, int count, 
     u[(long long)(c0 + c) * ls + k] = T(v);
 }
 
+// dst[i] = float(src[i]), i < n.
+__global__ void narrow_kernel(const double *__restrict__ src, float *__restrict__ dst, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
 }  // namespace
+
+hipError_t launch_narrow(const double *src, float *dst, long long n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(narrow_kernel, dim3((unsigned)nb), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_seed_slices(void *u, long long ls, int count, int S, long long nstep, unsigned long long seed,
                               int elem, hipStream_t st)

@@ -392,6 +392,8 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
         LevelInfo &L = P->lv[l];
         L.disp = take(dim * (size_t)L.N * S * 8);
         L.sigma = take(dim * (size_t)L.N * S * 8);
+        if (dim == 2 && d->precision == SLM_FP32_BULK && d->coarse_op == SLM_COARSE_MODIFIED)
+            L.sigma32 = take(dim * (size_t)L.N * S * 4);
         L.V = take(((size_t)L.N + 1) * S * el);
         L.G = take(((size_t)L.N + 1) * S * el);
         if (L.m) {
@@ -414,7 +416,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
         if (P->L > 1) {
             P->g2b = take(capg * S * el);
             P->g2v = take(capg * (SLM_KMAX + 1) * S * el);
-            P->g2w = take(capg * S * el);
+            P->g2w = take(2 * capg * S * el);             // w of two consecutive Arnoldi steps
             P->g2s = take(capg * sizeof(Gs2));
             P->g2p = take((3 * capg * (size_t)P->nb2 * SLM_NPART2 + 3 * capg * SLM_NPART2) * sizeof(double));
         }

@@ -307,5 +307,10 @@ hipError_t launch_backtrack_2d(const slm_plan &P, int l, hipStream_t st)
                        setup_disp(P, l - 1), l > 1 ? (const double *)ws_at(P, prev.sigma) : nullptr,
                        (double *)ws_at(P, cur.disp), (double *)ws_at(P, cur.sigma),
                        (long long)prev.N * P.S, (long long)cur.N * P.S);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !cur.sigma32) return e;
+    // FP32 bulk: the GMRES matvec reads sigma rounded to float (sigma itself
+    // stays FP64 and feeds the next level's recursion)
+    return launch_narrow((const double *)ws_at(P, cur.sigma), (float *)ws_at(P, cur.sigma32),
+                         2LL * cur.N * P.S, st);
 }
