@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--cpu-nt", type=int, default=4096, help="time steps of the CPU oracle sample")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--kernel-only", action="store_true",
-                    help="run only the level-0 F+C sweep kernel and a 1 GiB device copy (for counter runs)")
+                    help="run only the level-0 F+C sweep kernel (FP64 and FP32 bulk in 1D; FP32 bulk and one "
+                         "level-1 sweep with --workload 2d) and a 1 GiB device copy (for counter runs)")
     ap.add_argument("--workload", choices=["1d", "batch", "adjoint", "2d", "paper"], default="1d",
                     help="1d: the single 1D problem (default line); batch: 64 drawn 1D problems solved together; "
                          "adjoint: gradient of a final-time misfit for the 2D 256^2 problem; "
@@ -133,25 +134,49 @@ def batch_bench(args):
 
 
 def kernel_only(args):
-    """The dominant HBM kernel alone, plus a plain copy of known size whose
-    counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    """The dominant HBM kernel alone (level-0 F+C sweep of the 1D workload,
+    or with --workload 2d the 2D one, plus one level-1 sweep whose batched
+    GMRES kernels the counters also cover), each plan autotuned as in the
+    bench line, and a plain copy of known size whose counter readings
+    calibrate FETCH_SIZE / WRITE_SIZE."""
     import torch
     from paper_2203_13382_amd import Plan
     from paper_2203_13382_amd import inputs as I
     from paper_2203_13382_amd import workloads as W
-    pr, sv, _ = W.config(2)
-    plan = Plan(pr, sv, "fp64").setup()
-    ui = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 1)).cuda()
+    if args.workload == "2d":
+        pr, sv, prec = W.config(3)
+        dt = torch.float32
+    else:
+        pr, sv, _ = W.config(2)
+        prec, dt = "fp64", torch.float64
+    el = 8 if prec == "fp64" else 4
+    plan = Plan(pr, sv, prec).setup().autotune()
+    ui = torch.from_numpy(I.initial_iterate(pr.nt, pr.S, sv.m[0], 1)).to(device="cuda", dtype=dt)
     cin = ui[::sv.m[0]].contiguous()
     cout = torch.empty_like(cin)
     ms = timed(torch, lambda: plan.relax_into(0, "FC", c_in=cin, c_out=cout), args.kernel_reps)
+    nc = pr.nt // sv.m[0]
+    out = {"kernel": "level-0 F+C sweep", "workload": args.workload, "launch_ms": ms,
+           "launch_info": plan.launch_info(0, nc)}
+    if pr.dim == 1:
+        out["bytes_per_launch"] = el * pr.S * (pr.nt + 2 * nc + 1)
+        # the FP32-bulk plan's level-0 sweep (float displacements and slices)
+        p32 = Plan(pr, sv, "fp32").setup().autotune()
+        c32, o32 = cin.float(), torch.empty_like(cin, dtype=torch.float32)
+        out["fp32_launch_ms"] = timed(torch, lambda: p32.relax_into(0, "FC", c_in=c32, c_out=o32), args.kernel_reps)
+        out["fp32_bytes_per_launch"] = 4 * pr.S * (pr.nt + 2 * nc + 1)
+    else:
+        out["bytes_per_launch"] = el * pr.S * (4 * pr.nt + 2 * nc)
+        N1, m1 = plan.N[1], plan.m[1]
+        c1 = torch.randn(N1 // m1 + 1, pr.S, dtype=dt, device="cuda")
+        g1 = torch.randn(N1 + 1, pr.S, dtype=dt, device="cuda") * 1e-3
+        o1 = torch.empty_like(c1)
+        out["level1_sweep_ms"] = timed(torch, lambda: plan.relax_into(1, "FC", c_in=c1, g=g1, c_out=o1), 1, warm=0)
     src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)   # 1 GiB
     dst = torch.empty_like(src)
-    cms = timed(torch, lambda: dst.copy_(src), 3)
-    nc = pr.nt // sv.m[0]
-    print(json.dumps({"kernel": "fine1d level-0 FC sweep", "launch_ms": ms,
-                      "bytes_per_launch": 8 * pr.S * (pr.nt + 2 * nc + 1),
-                      "copy_bytes_each_way": src.numel() * 8, "copy_ms": cms}))
+    out["copy_ms"] = timed(torch, lambda: dst.copy_(src), 3)
+    out["copy_bytes_each_way"] = src.numel() * 8
+    print(json.dumps(out))
 
 
 def adjoint_bench(args):

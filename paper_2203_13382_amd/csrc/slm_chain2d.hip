@@ -23,6 +23,7 @@
 // coarse levels S_l^T [I - D_x diag(sx) - D_y diag(sy)]^{-1}: the GMRES
 // right-hand side is the incoming slice, the matvec the transposed one, and
 // the transposed interpolation follows the solve.
+#include <climits>
 #include <cmath>
 #include <type_traits>
 
@@ -165,6 +166,141 @@ __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ 
     }
 }
 
+// Coarse-level step with a per-tile window: a workgroup computes a WX x WY
+// tile of outputs.  It first reads the tile's departure points, then stages
+// in LDS the bounding box of all their stencils (periodically wrapped), so
+// the (p+1)^2-tap gathers hit LDS.  Coarse displacements are large but vary
+// slowly across a tile, so the box stays a small multiple of the tile.  A
+// tile whose box exceeds the LDS budget or the mesh gathers from global
+// memory instead.  Both paths form every output from interp2's products in
+// interp2's order, so the result never depends on the path.
+constexpr int WX = 64, WY = 16;
+constexpr int WIN_LDS_BYTES = 24 * 1024;
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = SLM_WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = SLM_WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <typename T, typename TD, int P>
+__global__ void __launch_bounds__(TPB) step2d_win_kernel(const T *__restrict__ src, long long src_stride,
+                                                         T *__restrict__ dst, long long dst_stride,
+                                                         const TD *__restrict__ disp, long long plane, int nx,
+                                                         long long n_first, int stride, const T *__restrict__ G,
+                                                         T *__restrict__ Vout)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *win = reinterpret_cast<T *>(smem_raw);
+    __shared__ int mm[4][TPB / SLM_WAVE];
+    constexpr int K = WX * WY / TPB;
+    const long long S = (long long)nx * nx;
+    const int c = blockIdx.y;
+    const long long n = n_first + (long long)c * stride;
+    const T *s = src + c * src_stride;
+    const int ntx = (nx + WX - 1) / WX;
+    const int x0 = (int)(blockIdx.x % ntx) * WX, y0 = (int)(blockIdx.x / ntx) * WY;
+    TD dxs[K], dys[K];
+    T ex[K], ey[K];
+    int gx[K], gy[K];
+    int xlo = INT_MAX, xhi = INT_MIN, ylo = INT_MAX, yhi = INT_MIN;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = threadIdx.x + k * TPB, i = x0 + e % WX, j = y0 + e / WX;
+        gx[k] = INT_MIN;
+        if (i < nx && j < nx) {
+            const long long id = (long long)j * nx + i;
+            const TD dx = disp[n * S + id], dy = disp[plane + n * S + id];
+            dxs[k] = dx;
+            dys[k] = dy;
+            const TD fx = floor(dx), fy = floor(dy);
+            ex[k] = T(dx - fx);
+            ey[k] = T(dy - fy);
+            gx[k] = i - int(fx) + stencil_first<T>(P, ex[k]);     // unwrapped stencil origin
+            gy[k] = j - int(fy) + stencil_first<T>(P, ey[k]);
+            xlo = min(xlo, gx[k]);
+            xhi = max(xhi, gx[k]);
+            ylo = min(ylo, gy[k]);
+            yhi = max(yhi, gy[k]);
+        }
+    }
+    const int wid = threadIdx.x / SLM_WAVE, lane = threadIdx.x % SLM_WAVE;
+    xlo = wave_min_i(xlo);
+    xhi = wave_max_i(xhi);
+    ylo = wave_min_i(ylo);
+    yhi = wave_max_i(yhi);
+    if (lane == 0) {
+        mm[0][wid] = xlo;
+        mm[1][wid] = xhi;
+        mm[2][wid] = ylo;
+        mm[3][wid] = yhi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < TPB / SLM_WAVE; ++w) {
+        xlo = min(xlo, mm[0][w]);
+        xhi = max(xhi, mm[1][w]);
+        ylo = min(ylo, mm[2][w]);
+        yhi = max(yhi, mm[3][w]);
+    }
+    // box of every stencil of the tile (the tile always holds a mesh node)
+    const long long bw = (long long)xhi - xlo + P + 1, bh = (long long)yhi - ylo + P + 1;
+    const bool staged = bw <= nx && bh <= nx && bw * bh * (long long)sizeof(T) <= WIN_LDS_BYTES;
+    if (staged) {
+        const int w = (int)bw, hgt = (int)bh;
+        int ox = xlo % nx, oy = ylo % nx;
+        ox += ox < 0 ? nx : 0;
+        oy += oy < 0 ? nx : 0;
+        for (int r = wid; r < hgt; r += TPB / SLM_WAVE) {          // one wave per box row
+            int gyy = oy + r;
+            gyy -= gyy >= nx ? nx : 0;
+            const T *row = s + (long long)gyy * nx;
+            for (int q = lane; q < w; q += SLM_WAVE) {
+                int gxx = ox + q;
+                gxx -= gxx >= nx ? nx : 0;
+                win[r * w + q] = row[gxx];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (gx[k] == INT_MIN) continue;
+        const int e = threadIdx.x + k * TPB, i = x0 + e % WX, j = y0 + e / WX;
+        const long long id = (long long)j * nx + i;
+        T v;
+        if (staged) {
+            const int w = (int)bw;
+            const int bx = gx[k] - xlo, by = gy[k] - ylo;
+            T wxv[P + 1], wyv[P + 1];
+            lagrange_weights<P, T>(-ex[k] - T(stencil_first<T>(P, ex[k])), wxv);
+            lagrange_weights<P, T>(-ey[k] - T(stencil_first<T>(P, ey[k])), wyv);
+            T acc = T(0);
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+                const T *row = win + (by + b) * w + bx;
+                T ar = T(0);
+#pragma unroll
+                for (int a = 0; a <= P; ++a) ar += wxv[a] * row[a];
+                acc += wyv[b] * ar;
+            }
+            v = acc;
+        } else {
+            v = interp2<P, T, TD>(s, i, j, dxs[k], dys[k], nx);
+        }
+        if (G) v += G[(n + 1) * S + id];
+        dst[c * dst_stride + id] = v;
+        if (Vout) Vout[(n + 1) * S + id] = v;
+    }
+}
+
 // Chain epilogue: Cout[c+shift] = last[c]; or residual R[c+1] = last[c] - Cref[c+1]
 // with per-(chain, block) partial sums of squares.
 template <typename T>
@@ -284,7 +420,8 @@ __global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long lo
 //   v = V_0 (j = 0) or w_{j-1} / hn_{j-1}, the previous step's vector
 //       normalised here (and stored as V_j) rather than in a launch of its own;
 //   w = v - sx .* (D_x v) - sy .* (D_y v), or for the adjoint system
-//       (transpose) w = v - D_x (sx .* v) - D_y (sy .* v);
+//       (transpose) w = v - D_x (sx .* v) - D_y (sy .* v), where the
+//       difference sums run over w_{j-1} and take the factor 1/hn_{j-1} once;
 // then the partials of the projections V_i . w (i <= j).  1D slices have
 // no y term.  The sigma of step n (or of Nl-1-n when rev) is read in TS: FP64,
 // or its float copy for FP32 bulk.
@@ -306,7 +443,6 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
         const double hn = gs[c].hn[j - 1];
         inv = hn > 0.0 ? 1.0 / hn : 0.0;
     }
-    auto ld = [&](long long ix) { return T(double(src[ix]) * inv); };   // V_j at node ix
     const TS *sx = sig + n * S, *sy = sig + plane + n * S;
     constexpr int q = DTaps<P>::q;
     double h[SLM_KMAX + 1];
@@ -323,16 +459,18 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
             ii += ii < 0 ? nx : 0;
             ii -= ii >= nx ? nx : 0;
             const long long ix = (long long)jr * nx + ii;
-            dxv += DTaps<P>::t[t + q] * (transpose ? double(sx[ix]) * double(ld(ix)) : double(ld(ix)));
+            dxv += DTaps<P>::t[t + q] * (transpose ? double(sx[ix]) * double(src[ix]) : double(src[ix]));
             if (dim == 2) {
                 int jj = jr + t;
                 jj += jj < 0 ? nx : 0;
                 jj -= jj >= nx ? nx : 0;
                 const long long iy = (long long)jj * nx + i;
-                dyv += DTaps<P>::t[t + q] * (transpose ? double(sy[iy]) * double(ld(iy)) : double(ld(iy)));
+                dyv += DTaps<P>::t[t + q] * (transpose ? double(sy[iy]) * double(src[iy]) : double(src[iy]));
             }
         }
-        const T vj = ld(id);
+        dxv *= inv;
+        dyv *= inv;
+        const T vj = T(double(src[id]) * inv);             // V_j at this node
         if (j > 0) Vc[(long long)j * S + id] = vj;
         const double yterm = dim == 2 ? (transpose ? dyv : double(sy[id]) * dyv) : 0.0;
         const T w = T(double(vj) - (transpose ? dxv : double(sx[id]) * dxv) - yterm);
@@ -522,6 +660,26 @@ hipError_t launch_step(int p, dim3 grid, hipStream_t st, const T *src, long long
     return hipGetLastError();
 }
 
+// Coarse-level step with per-tile stencil windows (step2d_win_kernel).
+template <typename T, typename TD>
+hipError_t launch_step_win(int p, int nch, hipStream_t st, const T *src, long long ss, T *dst, long long ds,
+                           const TD *disp, long long plane, int nx, long long n_first, int stride, const T *G,
+                           T *Vout)
+{
+    const dim3 grid(((nx + WX - 1) / WX) * ((nx + WY - 1) / WY), nch);
+#define STEPW(PP) hipLaunchKernelGGL((step2d_win_kernel<T, TD, PP>), grid, dim3(TPB), WIN_LDS_BYTES, st, src, ss, dst, \
+                                     ds, disp, plane, nx, n_first, stride, G, Vout)
+    switch (p) {
+    case 1: STEPW(1); break;
+    case 2: STEPW(2); break;
+    case 3: STEPW(3); break;
+    case 4: STEPW(4); break;
+    default: STEPW(5); break;
+    }
+#undef STEPW
+    return hipGetLastError();
+}
+
 // Level-0 step, LDS-tiled when the window of a tile fits (F from the bound
 // on the displacement); the plain gather kernel otherwise.
 // Halo F (cells) of the LDS-tiled level-0 step with tile shape `tile` for a
@@ -660,8 +818,9 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             if (e != hipSuccess) return e;
         } else if (level > 0 && P.d.coarse_op == SLM_COARSE_REDISC) {
             // rediscretized coarse operator: a plain SL step at the level's departure points
-            e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bufs[cur ^ 1], S, (const double *)ws_at(P, L.disp),
-                                       plane, nx, n_first0 + k, a.stride_chain, (const T *)a.G, vo);
+            e = launch_step_win<T, double>(P.d.p, nch, st, bufs[cur], S, bufs[cur ^ 1], S,
+                                           (const double *)ws_at(P, L.disp), plane, nx, n_first0 + k, a.stride_chain,
+                                           (const T *)a.G, vo);
             if (e != hipSuccess) return e;
         } else if (level == 0) {
             if (P.d.precision == SLM_FP32_BULK)
@@ -680,8 +839,8 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             if (a.adj) {
                 rhs = bufs[cur];
             } else {
-                e = launch_step<T, double>(P.d.p, grid, st, bufs[cur], S, bb, S, (const double *)ws_at(P, L.disp),
-                                           plane, nx, n_first0 + k, a.stride_chain, nullptr, nullptr);
+                e = launch_step_win<T, double>(P.d.p, nch, st, bufs[cur], S, bb, S, (const double *)ws_at(P, L.disp),
+                                               plane, nx, n_first0 + k, a.stride_chain, nullptr, nullptr);
                 if (e != hipSuccess) return e;
             }
             if (a.fwd) {                         // explicit correction, no linear solve
