@@ -483,6 +483,73 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
     if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
+// The same Arnoldi matvec for a 2D system whose mesh splits exactly into
+// the blocks' WX x WY tiles (forward operator only): the block stages its
+// tile of w_{j-1} (or V_0) with q cells of halo on every side in LDS, so the
+// 2(2q+1) difference taps of a node read LDS instead of the cache
+// hierarchy.  Per node the arithmetic is the untiled kernel's; only the
+// nodes each block's partial projections gather differ.
+template <typename T, typename TS, int P>
+__global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T *__restrict__ Wsrc,
+                                                       T *__restrict__ Wdst, long long S, int nx,
+                                                       const TS *__restrict__ sig, long long plane, long long n_first,
+                                                       int stride, int j, const Gs2 *gs, double *part)
+{
+    constexpr int q = DTaps<P>::q;
+    constexpr int HX = WX + 2 * q, HY = WY + 2 * q;
+    __shared__ T tile[HY * HX];
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.y;
+    if (gs[c].done) return;
+    const long long n = n_first + (long long)c * stride;
+    T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
+    const T *src = j == 0 ? Vc : Wsrc + (long long)c * S;
+    double inv = 1.0;
+    if (j > 0) {
+        const double hn = gs[c].hn[j - 1];
+        inv = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+    const TS *sx = sig + n * S, *sy = sig + plane + n * S;
+    const int ntx = nx / WX;
+    const int x0 = (int)(blockIdx.x % ntx) * WX, y0 = (int)(blockIdx.x / ntx) * WY;
+    for (int k = threadIdx.x; k < HX * HY; k += TPB) {
+        const int r = k / HX, cc = k - r * HX;
+        int gy = y0 - q + r, gx = x0 - q + cc;
+        gy += gy < 0 ? nx : 0;
+        gy -= gy >= nx ? nx : 0;
+        gx += gx < 0 ? nx : 0;
+        gx -= gx >= nx ? nx : 0;
+        tile[k] = src[(long long)gy * nx + gx];
+    }
+    __syncthreads();
+    double h[SLM_KMAX + 1];
+#pragma unroll
+    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
+#pragma unroll
+    for (int k = 0; k < WX * WY / TPB; ++k) {
+        const int e = threadIdx.x + k * TPB, lx = e % WX, ly = e / WX;
+        const long long id = (long long)(y0 + ly) * nx + x0 + lx;
+        const T *ctr = tile + (ly + q) * HX + lx + q;
+        double dxv = 0.0, dyv = 0.0;
+#pragma unroll
+        for (int t = -q; t <= q; ++t) {
+            dxv += DTaps<P>::t[t + q] * double(ctr[t]);
+            dyv += DTaps<P>::t[t + q] * double(ctr[t * HX]);
+        }
+        dxv *= inv;
+        dyv *= inv;
+        const T vj = T(double(*ctr) * inv);
+        if (j > 0) Vc[(long long)j * S + id] = vj;
+        const T w = T(double(vj) - double(sx[id]) * dxv - double(sy[id]) * dyv);
+        Wdst[c * S + id] = w;
+#pragma unroll
+        for (int kk = 0; kk <= SLM_KMAX; ++kk)
+            if (kk <= j) h[kk] += double(kk == j ? vj : Vc[(long long)kk * S + id]) * double(w);
+    }
+    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
+    if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+}
+
 // Givens recurrence of system g after Arnoldi step j: h = the Gram-Schmidt
 // coefficients, hn the norm of the orthogonalised vector (Sec. 3.3 GMRES,
 // same arithmetic order as the 1D kernel).  One thread.
@@ -746,11 +813,30 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
     return hipGetLastError();
 }
 
+// The LDS-tiled matvec applies when the forward 2D operator's mesh splits
+// exactly into the grid's WX x WY tiles, one per block.
+bool matvec_tiled(int dim, int transpose, int nx, int nb)
+{
+    return dim == 2 && !transpose && nx % WX == 0 && nx % WY == 0 && (nx / WX) * (nx / WY) == nb;
+}
+
 template <typename T, typename TS>
 hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, T *V, const T *Wsrc, T *Wdst, long long S, int nx,
                          const TS *sig, long long plane, long long n_first, int stride, int j, const Gs2 *gs,
                          double *part, int dim, int transpose, int rev, int Nl)
 {
+    if (matvec_tiled(dim, transpose, nx, (int)grid.x)) {
+#define MVT(PP) hipLaunchKernelGGL((g2_matvec_tile<T, TS, PP>), grid, dim3(TPB), 0, st, V, Wsrc, Wdst, S, nx, sig, \
+                                   plane, n_first, stride, j, gs, part)
+        switch (p) {
+        case 1: MVT(1); break;
+        case 3: MVT(3); break;
+        case 5: MVT(5); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef MVT
+        return hipGetLastError();
+    }
 #define MV(PP) hipLaunchKernelGGL((g2_matvec<T, TS, PP>), grid, dim3(TPB), 0, st, V, Wsrc, Wdst, S, nx, sig, plane, \
                                   n_first, stride, j, gs, part, dim, transpose, rev, Nl)
     switch (p) {
