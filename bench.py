@@ -319,7 +319,9 @@ def twod_bench(args):
     out["roofline"] = {"kernel": f"level-0 F+C sweep (LDS-tiled SL steps, tile choice {plan.tile_choice()})"
                                  if tiled else "level-0 F+C sweep (gather SL steps)",
                        "bound": "hbm", "achieved": l0["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": l0["frac"], "traffic": None, "launch_ms": l0["sweep_us"] * 1e-3,
+                       "frac": l0["frac"],
+                       "traffic": measured_traffic("cfg3_2d_kernels.md", ("slm_chain2d.hip", "slm_common.h")),
+                       "launch_ms": l0["sweep_us"] * 1e-3,
                        "bytes_per_launch": l0["bytes"]}
     print(json.dumps(out))
 
@@ -390,14 +392,15 @@ def paper_bench(args):
     print(json.dumps(out))
 
 
-def measured_traffic():
-    """HBM bytes per launch of the level-0 sweep from the committed counter
-    summary, or None once the kernel sources (device code of the sweep and
-    its helpers) differ from the ones profiled."""
+def measured_traffic(profile="cfg2_kernels.md",
+                     sources=("slm_kernels1d.h", "slm_chain1d.hip", "slm_fine1d.hip", "slm_common.h")):
+    """HBM bytes per launch of a workload's level-0 sweep from its committed
+    counter summary, or None once the kernel sources (device code of the
+    sweep and its helpers) differ from the ones profiled."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "cfg2_kernels.md")
+    prof = os.path.join(ROOT, "profiles", profile)
     csrc = os.path.join(ROOT, "paper_2203_13382_amd", "csrc")
-    srcs = [os.path.join(csrc, f) for f in ("slm_kernels1d.h", "slm_chain1d.hip", "slm_fine1d.hip", "slm_common.h")]
+    srcs = [os.path.join(csrc, f) for f in sources]
     try:
         kv = dict(line.split(": ", 1) for line in open(prof).read().splitlines() if ": " in line
                   and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_sha256_16"))
