@@ -484,24 +484,28 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
 }
 
 // The same Arnoldi matvec for a 2D system whose mesh splits exactly into
-// the blocks' WX x WY tiles (forward operator only): the block stages its
-// tile of w_{j-1} (or V_0) with q cells of halo on every side in LDS, so the
-// 2(2q+1) difference taps of a node read LDS instead of the cache
-// hierarchy.  Per node the arithmetic is the untiled kernel's; only the
-// nodes each block's partial projections gather differ.
-template <typename T, typename TS, int P>
+// the blocks' WX x WY tiles: the block stages its tile of w_{j-1} (or V_0)
+// with q cells of halo on every side in LDS, so the 2(2q+1) difference taps
+// of a node read LDS instead of the cache hierarchy.  The adjoint operator
+// (TRANS) differences sigma .* v: it stages the products sx .* v and
+// sy .* v, rounded as the untiled kernel rounds them.  Per node the
+// arithmetic is the untiled kernel's; only the nodes each block's partial
+// projections gather differ.
+template <typename T, typename TS, int P, bool TRANS>
 __global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T *__restrict__ Wsrc,
                                                        T *__restrict__ Wdst, long long S, int nx,
                                                        const TS *__restrict__ sig, long long plane, long long n_first,
-                                                       int stride, int j, const Gs2 *gs, double *part)
+                                                       int stride, int j, const Gs2 *gs, double *part, int rev, int Nl)
 {
     constexpr int q = DTaps<P>::q;
     constexpr int HX = WX + 2 * q, HY = WY + 2 * q;
-    __shared__ T tile[HY * HX];
+    using TT = typename std::conditional<TRANS, double, T>::type;   // staged type
+    __shared__ TT tile[TRANS ? 2 : 1][HY * HX];
     __shared__ double red[SLM_RED_DOUBLES];
     const int c = blockIdx.y;
     if (gs[c].done) return;
-    const long long n = n_first + (long long)c * stride;
+    const long long n0 = n_first + (long long)c * stride;
+    const long long n = rev ? Nl - 1 - n0 : n0;
     T *Vc = V + (long long)c * (SLM_KMAX + 1) * S;
     const T *src = j == 0 ? Vc : Wsrc + (long long)c * S;
     double inv = 1.0;
@@ -519,7 +523,13 @@ __global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T
         gy -= gy >= nx ? nx : 0;
         gx += gx < 0 ? nx : 0;
         gx -= gx >= nx ? nx : 0;
-        tile[k] = src[(long long)gy * nx + gx];
+        const long long g = (long long)gy * nx + gx;
+        if constexpr (TRANS) {
+            tile[0][k] = double(sx[g]) * double(src[g]);
+            tile[1][k] = double(sy[g]) * double(src[g]);
+        } else {
+            tile[0][k] = src[g];
+        }
     }
     __syncthreads();
     double h[SLM_KMAX + 1];
@@ -529,18 +539,19 @@ __global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T
     for (int k = 0; k < WX * WY / TPB; ++k) {
         const int e = threadIdx.x + k * TPB, lx = e % WX, ly = e / WX;
         const long long id = (long long)(y0 + ly) * nx + x0 + lx;
-        const T *ctr = tile + (ly + q) * HX + lx + q;
+        const int co = (ly + q) * HX + lx + q;
         double dxv = 0.0, dyv = 0.0;
 #pragma unroll
         for (int t = -q; t <= q; ++t) {
-            dxv += DTaps<P>::t[t + q] * double(ctr[t]);
-            dyv += DTaps<P>::t[t + q] * double(ctr[t * HX]);
+            dxv += DTaps<P>::t[t + q] * double(tile[0][co + t]);
+            dyv += DTaps<P>::t[t + q] * double(tile[TRANS ? 1 : 0][co + t * HX]);
         }
         dxv *= inv;
         dyv *= inv;
-        const T vj = T(double(*ctr) * inv);
+        const T vj = T(double(src[id]) * inv);
         if (j > 0) Vc[(long long)j * S + id] = vj;
-        const T w = T(double(vj) - double(sx[id]) * dxv - double(sy[id]) * dyv);
+        const T w = TRANS ? T(double(vj) - dxv - dyv)
+                          : T(double(vj) - double(sx[id]) * dxv - double(sy[id]) * dyv);
         Wdst[c * S + id] = w;
 #pragma unroll
         for (int kk = 0; kk <= SLM_KMAX; ++kk)
@@ -813,11 +824,11 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
     return hipGetLastError();
 }
 
-// The LDS-tiled matvec applies when the forward 2D operator's mesh splits
-// exactly into the grid's WX x WY tiles, one per block.
-bool matvec_tiled(int dim, int transpose, int nx, int nb)
+// The LDS-tiled matvec applies when the 2D mesh splits exactly into the
+// grid's WX x WY tiles, one per block.
+bool matvec_tiled(int dim, int nx, int nb)
 {
-    return dim == 2 && !transpose && nx % WX == 0 && nx % WY == 0 && (nx / WX) * (nx / WY) == nb;
+    return dim == 2 && nx % WX == 0 && nx % WY == 0 && (nx / WX) * (nx / WY) == nb;
 }
 
 template <typename T, typename TS>
@@ -825,14 +836,23 @@ hipError_t launch_matvec(int p, dim3 grid, hipStream_t st, T *V, const T *Wsrc, 
                          const TS *sig, long long plane, long long n_first, int stride, int j, const Gs2 *gs,
                          double *part, int dim, int transpose, int rev, int Nl)
 {
-    if (matvec_tiled(dim, transpose, nx, (int)grid.x)) {
-#define MVT(PP) hipLaunchKernelGGL((g2_matvec_tile<T, TS, PP>), grid, dim3(TPB), 0, st, V, Wsrc, Wdst, S, nx, sig, \
-                                   plane, n_first, stride, j, gs, part)
-        switch (p) {
-        case 1: MVT(1); break;
-        case 3: MVT(3); break;
-        case 5: MVT(5); break;
-        default: return hipErrorInvalidValue;
+    if (matvec_tiled(dim, nx, (int)grid.x)) {
+#define MVT(PP, TR) hipLaunchKernelGGL((g2_matvec_tile<T, TS, PP, TR>), grid, dim3(TPB), 0, st, V, Wsrc, Wdst, S, nx, \
+                                       sig, plane, n_first, stride, j, gs, part, rev, Nl)
+        if (transpose) {
+            switch (p) {
+            case 1: MVT(1, true); break;
+            case 3: MVT(3, true); break;
+            case 5: MVT(5, true); break;
+            default: return hipErrorInvalidValue;
+            }
+        } else {
+            switch (p) {
+            case 1: MVT(1, false); break;
+            case 3: MVT(3, false); break;
+            case 5: MVT(5, false); break;
+            default: return hipErrorInvalidValue;
+            }
         }
 #undef MVT
         return hipGetLastError();
