@@ -198,7 +198,15 @@ __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ s
     const double *lam = src + c * src_stride;
     const double *exs = eps + nd * S, *eys = eps + eplane + nd * S;
     const int *en = end + nd * S, *pm = perm + nd * S;
-    for (long long t = (long long)blockIdx.x * TPB + threadIdx.x; t < S; t += (long long)gridDim.x * TPB) {
+    // Each block takes a contiguous run of targets, and consecutive runs go
+    // to the same XCD (the dispatcher deals blocks to the 8 XCDs in turn):
+    // neighbouring target rows read overlapping cell lists, which then meet
+    // in one L2 instead of being fetched once per XCD.
+    const long long nb = gridDim.x, per = (S + nb - 1) / nb;
+    long long lb = blockIdx.x;
+    if ((nb & 7) == 0) lb = (lb & 7) * (nb >> 3) + (lb >> 3);
+    const long long t_end = (lb + 1) * per < S ? (lb + 1) * per : S;
+    for (long long t = lb * per + threadIdx.x; t < t_end; t += TPB) {
         int tx, ty;
         split_xy(t, nx, tx, ty);
         if (dim != 2) ty = 0;
