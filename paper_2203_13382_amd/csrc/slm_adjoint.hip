@@ -202,9 +202,7 @@ __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ s
     // to the same XCD (the dispatcher deals blocks to the 8 XCDs in turn):
     // neighbouring target rows read overlapping cell lists, which then meet
     // in one L2 instead of being fetched once per XCD.
-    const long long nb = gridDim.x, per = (S + nb - 1) / nb;
-    long long lb = blockIdx.x;
-    if ((nb & 7) == 0) lb = (lb & 7) * (nb >> 3) + (lb >> 3);
+    const long long nb = gridDim.x, per = (S + nb - 1) / nb, lb = xcd_block(blockIdx.x, nb);
     const long long t_end = (lb + 1) * per < S ? (lb + 1) * per : S;
     for (long long t = lb * per + threadIdx.x; t < t_end; t += TPB) {
         int tx, ty;

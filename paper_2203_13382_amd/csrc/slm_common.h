@@ -207,6 +207,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red, int buf)
 
 #define SLM_RED_DOUBLES (2 * (SLM_MAXB / SLM_WAVE) * 16)
 
+// The blocks of one grid row are dealt to the 8 XCDs in turn: with n blocks
+// per row (a multiple of 8) block b runs on XCD b % 8.  xcd_block maps the
+// physical index to a logical one so that each XCD takes a contiguous run of
+// logical blocks, and data shared by neighbouring blocks meets in one L2.
+// A bijection on [0, n); the identity when n is not a multiple of 8.
+__device__ __forceinline__ long long xcd_block(long long b, long long n)
+{
+    return (n & 7) ? b : (b & 7) * (n >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ double readlane_f64(double x, int lane)
 {
     const long long b = __double_as_longlong(x);
