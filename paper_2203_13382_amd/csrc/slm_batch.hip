@@ -56,7 +56,18 @@ struct BCopy {    // dst[c*ds + s] (+)= src[c*ss + s], c < count, s < S
 constexpr int CTL_THREADS = 1024;
 
 // ------------------------------------------------------------------ kernels
-__global__ void reset_counter(unsigned int *c) { if (threadIdx.x == 0) c[0] = 0u; }
+// Work-list counter of a persistent sweep: next[0] hands out items, next[1]
+// counts the workgroups that have left.  A workgroup leaves after its first
+// failed claim, so when the last one arrives no claim is pending and it sets
+// both back to zero for the next launch (which sees them at the kernel
+// boundary).  No launch is needed to reset them.
+__device__ __forceinline__ void leave_items(unsigned int *next)
+{
+    if (threadIdx.x == 0 && atomicAdd(next + 1, 1u) == gridDim.x - 1) {
+        atomicExch(next, 0u);
+        atomicExch(next + 1, 0u);
+    }
+}
 
 // Next work item of the workgroup (uniform).
 __device__ __forceinline__ int next_item(unsigned int *next)
@@ -85,6 +96,7 @@ __global__ void __launch_bounds__(SLM_MAXB) fine_batch(const BItem *items, int n
         fine_chain<T, TD, P, EPT, DBUF, PF>(a, items[it].j, smem);
         __syncthreads();
     }
+    leave_items(next);
 }
 
 template <typename T, int P, int EPT>
@@ -100,6 +112,7 @@ __global__ void __launch_bounds__(COARSE_MAXB) coarse_batch(const BItem *items, 
         coarse_chain<T, P, EPT>(a, items[it].j, smem);
         __syncthreads();
     }
+    leave_items(next);
 }
 
 // Stopping test of one active problem per workgroup; the residual norm is
@@ -414,12 +427,10 @@ hipError_t coarse_launch(const slm_batch &B, const slm_batch::Op &o, hipStream_t
 // One op on `st`; persistent sweeps pull items through counter slot `slot`.
 int run_op(slm_batch *B, const slm_batch::Op &o, hipStream_t st, int slot)
 {
-    unsigned *cnt = (unsigned *)(B->ws + B->o_counter) + slot;
+    unsigned *cnt = (unsigned *)(B->ws + B->o_counter) + 2 * slot;     // (next item, workgroups out)
     int *rem = (int *)(B->ws + B->o_remaining);
     BCtl *ctl = (BCtl *)(B->ws + B->o_ctl);
     if (o.kind == 0 || o.kind == 1) {
-        hipLaunchKernelGGL(reset_counter, dim3(1), dim3(64), 0, st, cnt);
-        BCHK(hipGetLastError());
         if (o.kind == 0) BCHK(B->fp32 ? fine_launch<float>(*B, o, st, cnt) : fine_launch<double>(*B, o, st, cnt));
         else BCHK(B->fp32 ? coarse_launch<float>(*B, o, st, cnt) : coarse_launch<double>(*B, o, st, cnt));
     } else if (o.kind == 2) {
@@ -703,7 +714,7 @@ int slm_batch_create(const slm_desc *descs, int n, slm_batch **out)
     B->o_ctl = off;
     off = al256(off + n * sizeof(BCtl));
     B->o_counter = off;
-    off = al256(off + 64 * sizeof(unsigned));
+    off = al256(off + 2 * 64 * sizeof(unsigned));
     B->o_remaining = off;
     off = al256(off + sizeof(int));
     B->o_hist = off;
@@ -857,6 +868,8 @@ int slm_batch_solve(slm_batch *B, const void *const *d_u0, void *const *d_u, slm
         maxit = std::max(maxit, P.d.max_iter);
         BCHK(hipMemsetAsync(ws_at(P, P.counter), 0, 2 * sizeof(unsigned long long), st));
     }
+    // work-list counters start at zero; every persistent sweep leaves them so
+    BCHK(hipMemsetAsync(B->ws + B->o_counter, 0, 2 * 64 * sizeof(unsigned), st));
     // start: C-point initial iterate (u_0 at C-point 0) and single-level
     // problems' sequential stepping, with every flag on
     B->hon = B->hctl;
