@@ -323,6 +323,8 @@ def twod_bench(args):
                        "traffic": measured_traffic("cfg3_2d_kernels.md", ("slm_chain2d.hip", "slm_common.h")),
                        "launch_ms": l0["sweep_us"] * 1e-3,
                        "bytes_per_launch": l0["bytes"]}
+    cr = copy_rate(torch)
+    out["roofline"].update({"copy_GBps": cr, "frac_of_copy": l0["GBps"] / cr})
     print(json.dumps(out))
 
 
@@ -408,6 +410,18 @@ def measured_traffic(profile="cfg2_kernels.md",
         return int(kv["traffic_bytes_per_launch"]) if kv.get("kernel_source_sha256_16", "").strip() == sha else None
     except (OSError, KeyError, ValueError):
         return None
+
+
+def copy_rate(torch):
+    """Read + write rate of a plain 1 GiB device-to-device copy (GB/s): the
+    practical ceiling a streaming kernel meets on this GPU, reported beside
+    the roofline fraction of the nominal peak."""
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = timed(torch, lambda: dst.copy_(src), 5)
+    rate = 2 * src.numel() * 8 / (ms * 1e-3) / 1e9
+    del src, dst
+    return rate
 
 
 def timed(torch, fn, reps, warm=1):
@@ -540,6 +554,9 @@ def main():
                      "achieved": k_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": k_gbs / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "launch_ms": k_ms, "bytes_per_launch": k_bytes},
     }
+
+    cr = copy_rate(torch)
+    out["roofline"].update({"copy_GBps": cr, "frac_of_copy": k_gbs / cr})
 
     # ---------------------------------------------------------------- FP32 bulk
     if not args.no_fp32:

@@ -413,8 +413,11 @@ static double dot(long long n, const double *a, const double *b)
  * (Sec. 3.3: ten iterations; Sec. 3.4 and 4.3: stop once the relative
  * residual is at most 1e-2 or after ten iterations).  Reading: no
  * preconditioner; Arnoldi with classical Gram-Schmidt (one pass: every
- * projection coefficient is taken of the same vector A v_j) and the new
- * vector's norm computed from the vector itself; Givens rotations for the
+ * projection coefficient is taken of the same vector w = A v_j).  The new
+ * vector's norm follows from the same pass by Pythagoras,
+ * ||w - V h||^2 = ||w||^2 - sum h_i^2 (V orthonormal), unless that
+ * difference is below 1e-3 ||w||^2, where cancellation would cost more than
+ * three digits: then it is computed from the updated vector.  Givens rotations for the
  * least-squares problem; the relative residual is the Givens estimate
  * |g_{j+1}|/||b||, tested after each iteration; rtol = 0 runs all kmax
  * iterations; b = 0 returns y = 0.  Returns the iterations done. */
@@ -457,11 +460,15 @@ static int bsolve_gen(int dim, int nx, int p, const double *sx, const double *sy
         if (transpose) slmo_apply_BT(dim, nx, p, sx, sy, V + (long long)j * S, w);
         else slmo_apply_B(dim, nx, p, sx, sy, V + (long long)j * S, w);
         for (int i = 0; i <= j; i++) hcol[i] = dot(S, V + (long long)i * S, w);   /* classical G-S */
+        double ww = dot(S, w, w);
         for (int i = 0; i <= j; i++) {
             const double *vi = V + (long long)i * S;
             for (long long t = 0; t < S; t++) w[t] -= hcol[i] * vi[t];
         }
-        double hn = sqrt(dot(S, w, w));
+        double hn2 = ww;                             /* Pythagoras */
+        for (int i = 0; i <= j; i++) hn2 -= hcol[i] * hcol[i];
+        if (!(hn2 >= 1e-3 * ww)) hn2 = dot(S, w, w); /* cancellation: the explicit norm */
+        double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
         for (int i = 0; i < j; i++) {                /* previous rotations */
             double t0 = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
             double t1 = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];

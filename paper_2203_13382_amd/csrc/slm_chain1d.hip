@@ -13,9 +13,11 @@
 // apply the modified operator of eq. (Phi_multilevel),
 //     v <- [I - diag(sigma) D_{p+1}]^{-1} S_{p,r*} v,
 // with the inverse applied by GMRES inside the workgroup (Sec. 3.3 / 3.4):
-// zero initial guess, Arnoldi with classical Gram-Schmidt (one pass) and
-// the new vector's norm reduced from the vector, Givens rotations, exit once
-// |g_{j+1}| <= rtol*||b|| or after kmax iterations.  Inner products and the Givens recurrence are FP64.  The
+// zero initial guess, Arnoldi with classical Gram-Schmidt (one pass) whose
+// reduction also carries ||w||^2, so that the new vector's norm follows by
+// Pythagoras (reduced from the updated vector where that would cancel),
+// Givens rotations, exit once |g_{j+1}| <= rtol*||b|| or after kmax
+// iterations.  Inner products and the Givens recurrence are FP64.  The
 // Krylov basis lives in registers (EPT values per thread per vector), so
 // coarse workgroups use at most 512 threads to get 256 VGPRs per lane.
 #include "slm_kernels1d.h"

@@ -422,8 +422,8 @@ __global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long lo
 //   w = v - sx .* (D_x v) - sy .* (D_y v), or for the adjoint system
 //       (transpose) w = v - D_x (sx .* v) - D_y (sy .* v), where the
 //       difference sums run over w_{j-1} and take the factor 1/hn_{j-1} once;
-// then the partials of the projections V_i . w (i <= j).  1D slices have
-// no y term.  The sigma of step n (or of Nl-1-n when rev) is read in TS: FP64,
+// then the partials of the projections V_i . w (i <= j) and of w . w (slot
+// j+1).  1D slices have no y term.  The sigma of step n (or of Nl-1-n when rev) is read in TS: FP64,
 // or its float copy for FP32 bulk.
 template <typename T, typename TS, int P>
 __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__restrict__ Wsrc, T *__restrict__ Wdst,
@@ -478,9 +478,10 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
 #pragma unroll
         for (int k = 0; k <= SLM_KMAX; ++k)
             if (k <= j) h[k] += double(k == j ? vj : Vc[(long long)k * S + id]) * double(w);
+            else if (k == j + 1) h[k] += double(w) * double(w);
     }
     block_sum_rs<SLM_KMAX + 1>(h, red, 0);
-    if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x <= j + 1) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
 // The same Arnoldi matvec for a 2D system whose mesh splits exactly into
@@ -556,9 +557,10 @@ __global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T
 #pragma unroll
         for (int kk = 0; kk <= SLM_KMAX; ++kk)
             if (kk <= j) h[kk] += double(kk == j ? vj : Vc[(long long)kk * S + id]) * double(w);
+            else if (kk == j + 1) h[kk] += double(w) * double(w);
     }
     block_sum_rs<SLM_KMAX + 1>(h, red, 0);
-    if (threadIdx.x <= j) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+    if (threadIdx.x <= j + 1) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
 // Givens recurrence of system g after Arnoldi step j: h = the Gram-Schmidt
@@ -615,15 +617,39 @@ __global__ void __launch_bounds__(TPB) g2_update(const T *__restrict__ V, T *__r
     if (threadIdx.x == 0) part[((long long)c * nb + blockIdx.x) * NPART] = h[0];
 }
 
-// ||w|| of every system from the update's partials (one workgroup per
-// system, fixed order), then the Givens step, which may end the system's
-// iteration.  h1: the reduced projections.
+// Totals of the matvec's partials (projections h and ||w||^2, one workgroup
+// per system, fixed order) into h1; the new vector's norm by Pythagoras,
+// ||w - V h||^2 = ||w||^2 - sum h_i^2, and the Givens step, unless that
+// difference is below 1e-3 ||w||^2: then the system is marked to take its
+// norm from the updated vector (g2_norm_givens).
+__global__ void __launch_bounds__(TPB) g2_sum_givens(const double *__restrict__ part, int nb, Gs2 *gs, int j,
+                                                     double *__restrict__ h1, double rtol, int kmax)
+{
+    __shared__ double red[SLM_RED_DOUBLES];
+    const int c = blockIdx.x;
+    if (gs[c].done) return;
+    double v[SLM_KMAX + 1];
+    sum_parts(part, nb, j + 2, c, v, red, 0);
+    if (threadIdx.x <= j + 1) h1[(long long)c * NPART + threadIdx.x] = v[threadIdx.x];
+    if (threadIdx.x == 0) {
+        const double ww = v[j + 1];
+        double hn2 = ww;
+        for (int i = 0; i <= j; ++i) hn2 -= v[i] * v[i];
+        Gs2 &g = gs[c];
+        g.need = !(hn2 >= 1e-3 * ww);
+        if (!g.need) givens_step(g, j, v, sqrt(hn2 > 0.0 ? hn2 : 0.0), rtol, kmax);
+    }
+}
+
+// The explicit norm for the systems g2_sum_givens marked: ||w|| from the
+// update's partials (one workgroup per system, fixed order), then the Givens
+// step.  h1: the reduced projections.
 __global__ void __launch_bounds__(TPB) g2_norm_givens(const double *__restrict__ part, int nb, Gs2 *gs, int j,
                                                       const double *__restrict__ h1, double rtol, int kmax)
 {
     __shared__ double red[SLM_RED_DOUBLES];
     const int c = blockIdx.x;
-    if (gs[c].done) return;
+    if (gs[c].done || !gs[c].need) return;
     double v[SLM_KMAX + 1];
     sum_parts(part, nb, 1, c, v, red, 0);
     if (threadIdx.x == 0) givens_step(gs[c], j, h1 + (long long)c * NPART, sqrt(v[0]), rtol, kmax);
@@ -967,10 +993,12 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
             hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, 1, (const Gs2 *)nullptr, r3);
             hipLaunchKernelGGL(g2_start<T>, grid, dim3(TPB), 0, st, rhs, S, r3, V, gs, a.kmax);
             // Arnoldi step j: the matvec (normalising w_{j-1} on the fly) with
-            // the partial projections, their totals, classical Gram-Schmidt
-            // w -= V h with the partials of ||w||^2, then ||w|| and the Givens
-            // step.  w alternates between two buffers so the matvec's stencil
-            // reads w_{j-1} while it writes w_j.
+            // the partial projections and ||w||^2; their totals, the norm by
+            // Pythagoras and the Givens step; classical Gram-Schmidt
+            // w -= V h with the partials of ||w - V h||^2; the explicit norm
+            // and Givens step where Pythagoras would cancel.  w alternates
+            // between two buffers so the matvec's stencil reads w_{j-1} while
+            // it writes w_j.
             for (int j = 0; j < a.kmax; ++j) {
                 T *Wsrc = Wb2[(j + 1) & 1], *Wdst = Wb2[j & 1];
                 bool done = false;
@@ -987,7 +1015,7 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                                                  (const double *)ws_at(P, L.sigma), plane, n_first0 + k,
                                                  a.stride_chain, j, gs, pa, P.d.dim, a.adj, a.adj, L.N);
                 if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(g2_sum, dim3(nch), dim3(TPB), 0, st, pa, nb, j + 1, gs, r1);
+                hipLaunchKernelGGL(g2_sum_givens, dim3(nch), dim3(TPB), 0, st, pa, nb, gs, j, r1, a.rtol, a.kmax);
                 hipLaunchKernelGGL(g2_update<T>, grid, dim3(TPB), 0, st, V, Wdst, S, j, gs, r1, pc);
                 hipLaunchKernelGGL(g2_norm_givens, dim3(nch), dim3(TPB), 0, st, pc, nb, gs, j, r1, a.rtol, a.kmax);
             }

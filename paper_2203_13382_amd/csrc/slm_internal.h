@@ -30,6 +30,7 @@ struct Gs2 {
     double beta;
     int k;                           // iterations done
     int done;
+    int need;                        // the step's norm must be reduced from the updated vector
 };
 #define SLM_NPART2 16
 

@@ -323,10 +323,12 @@ struct Gmres1D {
                 w[e] = T(0);
             }
         }
-        // classical Gram-Schmidt (every coefficient projects the same w);
-        // inner products are wave-uniform.  The new vector's norm is reduced
-        // from the updated vector itself.
-        double h1[JJ + 1];
+        // classical Gram-Schmidt (every coefficient projects the same w) and
+        // ||w||^2 in one reduction; the new vector's norm then follows by
+        // Pythagoras, ||w - V h||^2 = ||w||^2 - sum h_i^2, unless cancellation
+        // would cost more than three digits: then a second reduction takes it
+        // from the updated vector.  Inner products are wave-uniform.
+        double h1[JJ + 2];
 #pragma unroll
         for (int i = 0; i <= JJ; ++i) {
             double s = 0.0;
@@ -334,7 +336,13 @@ struct Gmres1D {
             for (int e = 0; e < EPT; ++e) s += double(V[i][e] * w[e]);   // FP32 bulk: product in T
             h1[i] = s;
         }
-        block_sum_u<JJ + 1>(h1, red, rb);
+        {
+            double s = 0.0;
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) s += double(w[e] * w[e]);
+            h1[JJ + 1] = s;
+        }
+        block_sum_u<JJ + 2>(h1, red, rb);
         rb ^= 1;
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
@@ -343,12 +351,17 @@ struct Gmres1D {
             for (int i = 0; i <= JJ; ++i) t -= T(h1[i]) * V[i][e];
             w[e] = t;
         }
-        double nn[1] = {0.0};
+        double hn2 = h1[JJ + 1];
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) nn[0] += double(w[e] * w[e]);
-        block_sum_u<1>(nn, red, rb);
-        rb ^= 1;
-        const double hn2 = nn[0];
+        for (int i = 0; i <= JJ; ++i) hn2 -= h1[i] * h1[i];
+        if (!(hn2 >= 1e-3 * h1[JJ + 1])) {
+            double nn[1] = {0.0};
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) nn[0] += double(w[e] * w[e]);
+            block_sum_u<1>(nn, red, rb);
+            rb ^= 1;
+            hn2 = nn[0];
+        }
         const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
         if (tid == 0) {
             double hc[JJ + 1];

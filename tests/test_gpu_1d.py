@@ -88,6 +88,15 @@ def test_setup_arrays(name, oracle, torch, built):
             assert np.abs(s_gpu - s_ora).max() < 1e-9 * max(1.0, np.abs(s_ora).max()), l
 
 
+def _phi_tol(sv, level):
+    """Agreement of one level step with the oracle's.  With rtol = 0 GMRES
+    keeps iterating after it has converged; the Krylov basis of one-pass
+    Gram-Schmidt then loses orthogonality, and the Pythagorean norm amplifies
+    that loss by ||w||^2 / hn^2 (at most 1e3 before the explicit norm takes
+    over), so the two sides' roundings of it part at about 1e-8."""
+    return 1e-7 if level > 0 and sv.gmres_rtol == 0.0 else 1e-11
+
+
 @pytest.mark.parametrize("name", CASES)
 def test_apply_phi_every_level(name, oracle, torch, built):
     pr, sv, plan, ctx = _setup(name, oracle)
@@ -98,7 +107,7 @@ def test_apply_phi_every_level(name, oracle, torch, built):
         xin = rng.standard_normal((cnt, pr.S))
         out = plan.apply_phi(l, n0, torch.from_numpy(xin)).cpu().numpy()
         ref = np.stack([ctx.apply_phi(l, n0 + k, xin[k]) for k in range(cnt)])
-        assert _rel(out, ref) < 1e-11, (l, _rel(out, ref))
+        assert _rel(out, ref) < _phi_tol(sv, l), (l, _rel(out, ref))
 
 
 @pytest.mark.parametrize("name", CASES)

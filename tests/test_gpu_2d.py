@@ -94,7 +94,9 @@ def test_apply_phi_every_level(name, oracle, torch):
         xin = rng.standard_normal((cnt, pr.S))
         out = plan.apply_phi(l, n0, torch.from_numpy(xin)).cpu().numpy()
         ref = np.stack([ctx.apply_phi(l, n0 + k, xin[k]) for k in range(cnt)])
-        assert _rel(out, ref) < 1e-11, (l, _rel(out, ref))
+        # rtol = 0: GMRES past convergence, see test_gpu_1d._phi_tol
+        tol = 1e-7 if l > 0 and sv.gmres_rtol == 0.0 else 1e-11
+        assert _rel(out, ref) < tol, (l, _rel(out, ref))
 
 
 @pytest.mark.parametrize("name", CASES)
