@@ -33,6 +33,7 @@ namespace {
 
 constexpr int TPB = 256;            // threads per block of the point kernels
 constexpr int NPART = 16;           // partial-sum slots per block
+constexpr int WWS = SLM_KMAX + 1;   // slot of ||w||^2 beside the projections 0..j
 
 // ------------------------------------------------------------ interpolation
 template <int P, typename T, typename TD>
@@ -367,18 +368,19 @@ __global__ void __launch_bounds__(TPB) g2_norm0(const T *__restrict__ b, long lo
 // Fixed-order reduction of the per-block partials of system c: one
 // workgroup sums the nb blocks' slots q < nv (each thread a strided subset,
 // then a deterministic workgroup tree); every thread receives the totals.
-__device__ __forceinline__ void sum_parts(const double *part, int nb, int nv, int c, double (&v)[SLM_KMAX + 1],
-                                          double *red, int buf)
+template <int NV>
+__device__ __forceinline__ void sum_parts(const double *part, int nb, int nv, int c, double (&v)[NV], double *red,
+                                          int buf)
 {
 #pragma unroll
-    for (int q = 0; q <= SLM_KMAX; ++q) v[q] = 0.0;
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;
     for (int b = threadIdx.x; b < nb; b += TPB) {
         const double *pp = part + ((long long)c * nb + b) * NPART;
 #pragma unroll
-        for (int q = 0; q <= SLM_KMAX; ++q)
+        for (int q = 0; q < NV; ++q)
             if (q < nv) v[q] += pp[q];
     }
-    block_sum_rs<SLM_KMAX + 1>(v, red, buf);
+    block_sum_rs<NV>(v, red, buf);
 }
 
 // Totals of the per-block partials, one workgroup per system, into
@@ -422,8 +424,8 @@ __global__ void __launch_bounds__(TPB) g2_start(const T *__restrict__ b, long lo
 //   w = v - sx .* (D_x v) - sy .* (D_y v), or for the adjoint system
 //       (transpose) w = v - D_x (sx .* v) - D_y (sy .* v), where the
 //       difference sums run over w_{j-1} and take the factor 1/hn_{j-1} once;
-// then the partials of the projections V_i . w (i <= j) and of w . w (slot
-// j+1).  1D slices have no y term.  The sigma of step n (or of Nl-1-n when rev) is read in TS: FP64,
+// then the partials of the projections V_i . w (i <= j, zero above) and of
+// w . w (slot WWS).  1D slices have no y term.  The sigma of step n (or of Nl-1-n when rev) is read in TS: FP64,
 // or its float copy for FP32 bulk.
 template <typename T, typename TS, int P>
 __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__restrict__ Wsrc, T *__restrict__ Wdst,
@@ -445,9 +447,9 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
     }
     const TS *sx = sig + n * S, *sy = sig + plane + n * S;
     constexpr int q = DTaps<P>::q;
-    double h[SLM_KMAX + 1];
+    double h[WWS + 1];
 #pragma unroll
-    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
+    for (int i = 0; i <= WWS; ++i) h[i] = 0.0;
     for (long long id = (long long)blockIdx.x * TPB + threadIdx.x; id < S; id += (long long)gridDim.x * TPB) {
         int i, jr;
         split_xy(id, nx, i, jr);
@@ -478,10 +480,10 @@ __global__ void __launch_bounds__(TPB) g2_matvec(T *__restrict__ V, const T *__r
 #pragma unroll
         for (int k = 0; k <= SLM_KMAX; ++k)
             if (k <= j) h[k] += double(k == j ? vj : Vc[(long long)k * S + id]) * double(w);
-            else if (k == j + 1) h[k] += double(w) * double(w);
+        h[WWS] += double(w) * double(w);
     }
-    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
-    if (threadIdx.x <= j + 1) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+    block_sum_rs<WWS + 1>(h, red, 0);
+    if (threadIdx.x <= WWS) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
 // The same Arnoldi matvec for a 2D system whose mesh splits exactly into
@@ -533,9 +535,9 @@ __global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T
         }
     }
     __syncthreads();
-    double h[SLM_KMAX + 1];
+    double h[WWS + 1];
 #pragma unroll
-    for (int i = 0; i <= SLM_KMAX; ++i) h[i] = 0.0;
+    for (int i = 0; i <= WWS; ++i) h[i] = 0.0;
 #pragma unroll
     for (int k = 0; k < WX * WY / TPB; ++k) {
         const int e = threadIdx.x + k * TPB, lx = e % WX, ly = e / WX;
@@ -557,10 +559,10 @@ __global__ void __launch_bounds__(TPB) g2_matvec_tile(T *__restrict__ V, const T
 #pragma unroll
         for (int kk = 0; kk <= SLM_KMAX; ++kk)
             if (kk <= j) h[kk] += double(kk == j ? vj : Vc[(long long)kk * S + id]) * double(w);
-            else if (kk == j + 1) h[kk] += double(w) * double(w);
+        h[WWS] += double(w) * double(w);
     }
-    block_sum_rs<SLM_KMAX + 1>(h, red, 0);
-    if (threadIdx.x <= j + 1) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
+    block_sum_rs<WWS + 1>(h, red, 0);
+    if (threadIdx.x <= WWS) part[((long long)c * gridDim.x + blockIdx.x) * NPART + threadIdx.x] = h[threadIdx.x];
 }
 
 // Givens recurrence of system g after Arnoldi step j: h = the Gram-Schmidt
@@ -628,11 +630,11 @@ __global__ void __launch_bounds__(TPB) g2_sum_givens(const double *__restrict__ 
     __shared__ double red[SLM_RED_DOUBLES];
     const int c = blockIdx.x;
     if (gs[c].done) return;
-    double v[SLM_KMAX + 1];
-    sum_parts(part, nb, j + 2, c, v, red, 0);
-    if (threadIdx.x <= j + 1) h1[(long long)c * NPART + threadIdx.x] = v[threadIdx.x];
+    double v[WWS + 1];
+    sum_parts(part, nb, WWS + 1, c, v, red, 0);
+    if (threadIdx.x <= j) h1[(long long)c * NPART + threadIdx.x] = v[threadIdx.x];
     if (threadIdx.x == 0) {
-        const double ww = v[j + 1];
+        const double ww = v[WWS];
         double hn2 = ww;
         for (int i = 0; i <= j; ++i) hn2 -= v[i] * v[i];
         Gs2 &g = gs[c];
