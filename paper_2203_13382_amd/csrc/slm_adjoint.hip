@@ -210,20 +210,33 @@ __global__ void __launch_bounds__(TPB) stepT_kernel(const double *__restrict__ s
         if (dim != 2) ty = 0;
         double acc = 0.0;
         const int nby = dim == 2 ? P : 0;
-        for (int b = 0; b <= nby; ++b) {
+        // the source ranges of all the target's cells first (independent
+        // loads), then the sources cell by cell in the same order as before
+        int lo[P + 1][P + 1], hi[P + 1][P + 1];
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
             int ey = 0;
             if (dim == 2) {
                 ey = ty + ell - b;
                 ey += ey < 0 ? nx : 0;
                 ey -= ey >= nx ? nx : 0;
             }
+#pragma unroll
             for (int a = 0; a <= P; ++a) {
                 int ex = tx + ell - a;
                 ex += ex < 0 ? nx : 0;
                 ex -= ex >= nx ? nx : 0;
                 const long long cell = (long long)ey * nx + ex;
-                const int lo = cell ? en[cell - 1] : 0, hi = en[cell];
-                for (int q = lo; q < hi; ++q) {
+                lo[b][a] = (b <= nby && cell) ? en[cell - 1] : 0;
+                hi[b][a] = b <= nby ? en[cell] : 0;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+            if (b > nby) break;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) {
+                for (int q = lo[b][a]; q < hi[b][a]; ++q) {
                     double wv = lweight<P>(-exs[q] + (double)ell, a);
                     if (dim == 2) wv *= lweight<P>(-eys[q] + (double)ell, b);
                     acc += wv * lam[pm[q]];
