@@ -42,6 +42,7 @@ struct slm_plan {
     int L = 0;                          // number of levels
     LevelInfo lv[SLM_MAX_LEVELS];
     size_t C0b = 0;                     // second level-0 C-point buffer
+    size_t stab = 0;                    // [nt][6 stages][2 fields][SLM_MAX_TERMS] stage factors of the fine trace
     size_t partial = 0;                 // [max intervals] double
     size_t norm = 0;                    // 1 double
     size_t counter = 0;                 // 2 x uint64: gmres solves, iterations

@@ -381,6 +381,7 @@ int slm_plan_create(const slm_desc *d, slm_plan **out)
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + (bytes ? bytes : 1)); return o; };
     LevelInfo &L0 = P->lv[0];
     L0.disp = take(dim * (size_t)d->nt * S * (d->precision == SLM_FP32_BULK ? 4 : 8));
+    P->stab = take((size_t)d->nt * 6 * 2 * SLM_MAX_TERMS * sizeof(double));
     if (d->precision == SLM_FP32_BULK) L0.disp64 = take(dim * (size_t)d->nt * S * 8);
     size_t maxc = 1;
     if (P->L > 1) {

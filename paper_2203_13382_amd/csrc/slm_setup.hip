@@ -69,14 +69,35 @@ __device__ __forceinline__ double node_eval(const WaveField &f, const double (&u
     return s;
 }
 
-// Fine departure trace: trace_npt nodes of one step per thread, so that the
-// per-stage factors are evaluated once for all of them.
+// The stage factors of every fine step (stage_factors for step n, stage s,
+// field f, term k at tab[((n*6 + s)*2 + f)*SLM_MAX_TERMS + k]): the same for
+// every node of the step, so they are evaluated once here instead of in
+// every thread of the trace.
+template <int R, int DIM>
+__global__ void stage_table_kernel(int nt, double dt, WaveField fa, WaveField fb, double *tab)
+{
+    const Erk e = erk_tableau(R);
+    const int n = blockIdx.x;
+    if (n >= nt) return;
+    const double hs = -dt, t_arr = (n + 1) * dt;
+    for (int i = threadIdx.x; i < e.s * 2; i += blockDim.x) {
+        const int s = i >> 1, f = i & 1;
+        const double ts = t_arr + e.c[s] * hs;
+        double u[SLM_MAX_TERMS];
+        stage_factors<DIM>(f ? fb : fa, ts, u);
+        double *o = tab + (((long long)n * 6 + s) * 2 + f) * SLM_MAX_TERMS;
+        for (int k = 0; k < (f ? fb.n : fa.n); ++k) o[k] = u[k];
+    }
+}
+
+// Fine departure trace: trace_npt nodes of one step per thread.
 template <int DIM>
-constexpr int trace_npt() { return DIM == 1 ? 4 : 2; }
+constexpr int trace_npt() { return DIM == 1 ? 2 : 1; }
 
 template <int R, int DIM>
 __global__ void __launch_bounds__(256) trace_kernel(int nx, long long S, int nt, double dt, double h, WaveField fa,
-                                                    WaveField fb, double *out64, float *out32)
+                                                    WaveField fb, const double *__restrict__ tab, double *out64,
+                                                    float *out32)
 {
     constexpr int NPT = trace_npt<DIM>();
     const Erk e = erk_tableau(R);
@@ -95,9 +116,10 @@ __global__ void __launch_bounds__(256) trace_kernel(int nx, long long S, int nt,
     double ua[SLM_MAX_TERMS], ub[SLM_MAX_TERMS];
 #pragma unroll
     for (int s = 0; s < e.s; ++s) {
-        const double ts = t_arr + e.c[s] * hs;
-        stage_factors<DIM>(fa, ts, ua);
-        if (DIM == 2) stage_factors<DIM>(fb, ts, ub);
+        const double *ts = tab + ((long long)n * 6 + s) * 2 * SLM_MAX_TERMS;
+        for (int k = 0; k < fa.n; ++k) ua[k] = ts[k];
+        if (DIM == 2)
+            for (int k = 0; k < fb.n; ++k) ub[k] = ts[SLM_MAX_TERMS + k];
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             double X = x[j], Y = y[j];
@@ -248,14 +270,22 @@ hipError_t trace_dispatch(const slm_plan &P, hipStream_t st)
     float *o32 = f32 ? (float *)ws_at(P, L0.disp) : nullptr;
     const double h = 2.0 / P.d.nx;
     constexpr int NPT = trace_npt<DIM>();
+    double *tab = (double *)ws_at(P, P.stab);
     dim3 grid((unsigned)((P.S + 256 * NPT - 1) / (256 * NPT)), (unsigned)P.d.nt);
+#define TR(RR) do { \
+        hipLaunchKernelGGL((stage_table_kernel<RR, DIM>), dim3((unsigned)P.d.nt), dim3(64), 0, st, P.d.nt, P.d.dt, \
+                           P.fa, P.fb, tab); \
+        hipLaunchKernelGGL((trace_kernel<RR, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, \
+                           h, P.fa, P.fb, (const double *)tab, o64, o32); \
+    } while (0)
     switch (P.d.r) {
-    case 1: hipLaunchKernelGGL((trace_kernel<1, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
-    case 2: hipLaunchKernelGGL((trace_kernel<2, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
-    case 3: hipLaunchKernelGGL((trace_kernel<3, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
-    case 4: hipLaunchKernelGGL((trace_kernel<4, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
-    default: hipLaunchKernelGGL((trace_kernel<5, DIM>), grid, dim3(256), 0, st, P.d.nx, (long long)P.S, P.d.nt, P.d.dt, h, P.fa, P.fb, o64, o32); break;
+    case 1: TR(1); break;
+    case 2: TR(2); break;
+    case 3: TR(3); break;
+    case 4: TR(4); break;
+    default: TR(5); break;
     }
+#undef TR
     return hipGetLastError();
 }
 
