@@ -1,0 +1,291 @@
+"""GPU parity of the degenerate and extreme cases of the method against the
+FP64 oracle, through the C ABI.
+
+* the smallest meshes (nx = 8, in 1D and 2D) with the deepest hierarchy m = 2
+  allows;
+* departure points that wrap the periodic mesh several times (CFL well
+  above nx), the plain-gather path of both dimensions;
+* hierarchies that stop early: nt = 1 and nt not divisible by m (one level,
+  sequential stepping), m = nt (one coarse step), a coarsest level whose
+  step count is not a multiple of m;
+* a zero velocity field (every SL step is the identity, sigma = 0 and the
+  coarse system is I), and a constant velocity at integer CFL, where the
+  departure points fall on mesh nodes and the floor of the displacement
+  decides the interpolation stencil;
+* zero data (u0 = 0 and a zero initial iterate: rho_0 = 0);
+* the largest 2D mesh the library accepts (4096^2), checked on whole slices
+  of the setup arrays and steps and, for MGRIT, by the property that it
+  reaches sequential stepping.
+"""
+import numpy as np
+import pytest
+
+from paper_2203_13382_amd import inputs as I
+from paper_2203_13382_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    a3, b3 = W.field_cfg3()
+    cases = {
+        "min_nx8_1d": (W.Problem(1, 8, 16, 0.5 * 2 / 8, 3, 3, W.alpha_cfg12()), W.Solver(m=[2])),
+        "wrap_many_1d": (W.Problem(1, 16, 32, 20.0 * 2 / 16, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
+        "nt1_1d": (W.Problem(1, 64, 1, 0.85 * 2 / 64, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
+        "nt17_1d": (W.Problem(1, 64, 17, 0.85 * 2 / 64, 5, 5, W.alpha_cfg12()), W.Solver(m=[4])),
+        "m_eq_nt_1d": (W.Problem(1, 96, 16, 2.5 * 2 / 96, 3, 3, W.alpha_cfg12()), W.Solver(m=[16])),
+        "ragged_coarsest_1d": (W.Problem(1, 128, 24, 1.5 * 2 / 128, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
+        "alpha0_1d": (W.Problem(1, 64, 64, 0.85 * 2 / 64, 3, 3, [W.term(0.0)]), W.Solver(m=[4])),
+        "int_cfl_1d": (W.Problem(1, 64, 64, 2 * 2 / 64, 5, 5, [W.term(1.0)]), W.Solver(m=[4])),
+        "min_nx8_2d": (W.Problem(2, 8, 8, 0.5 * 2 / 8, 3, 3, a3, b3), W.Solver(m=[2])),
+        "wrap_many_2d": (W.Problem(2, 16, 16, 20.0 * 2 / 16, 3, 3, [W.term(1.0), W.term(0.3, ky=1.0, kt=1.0)],
+                                   [W.term(-1.0), W.term(0.3, kx=1.0)]), W.Solver(m=[4])),
+        "field0_2d": (W.Problem(2, 16, 16, 1.0 * 2 / 16, 5, 5, [W.term(0.0)], [W.term(0.0)]), W.Solver(m=[4])),
+        "int_cfl_2d": (W.Problem(2, 16, 16, 2 * 2 / 16, 3, 3, [W.term(1.0)], [W.term(-1.0)]), W.Solver(m=[4])),
+    }
+    return cases[name]
+
+
+CASES = ["min_nx8_1d", "wrap_many_1d", "nt1_1d", "nt17_1d", "m_eq_nt_1d", "ragged_coarsest_1d", "alpha0_1d",
+         "int_cfl_1d", "min_nx8_2d", "wrap_many_2d", "field0_2d", "int_cfl_2d"]
+
+# the level hierarchy each case must build (number of steps per level)
+LEVELS = {"min_nx8_1d": [16, 8, 4, 2, 1], "nt1_1d": [1], "nt17_1d": [17], "m_eq_nt_1d": [16, 1],
+          "ragged_coarsest_1d": [24, 6], "min_nx8_2d": [8, 4, 2, 1]}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+_cache = {}
+
+
+def _setup(name, oracle):
+    if name not in _cache:
+        from paper_2203_13382_amd import Plan
+        pr, sv = _case(name)
+        print(f"edge case {name}: dim={pr.dim} nx={pr.nx} nt={pr.nt} p={pr.p} m={sv.m}", flush=True)
+        plan = Plan(pr, sv, "fp64").setup()
+        ctx = oracle.Context(pr, sv)
+        _cache[name] = (pr, sv, plan, ctx)
+    return _cache[name]
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(1e-300, np.abs(b).max())
+
+
+def _coords(pr):
+    idx = np.arange(pr.S)
+    if pr.dim == 1:
+        return [-1 + idx * pr.h]
+    return [-1 + (idx % pr.nx) * pr.h, -1 + (idx // pr.nx) * pr.h]
+
+
+def _dep(ctx, pr, l, c):
+    return ctx.dep(l) if pr.dim == 1 else ctx.dep(l, c)
+
+
+def _sigma(ctx, pr, l, c):
+    return ctx.sigma(l) if pr.dim == 1 else ctx.sigma(l, c)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_setup_arrays(name, oracle, torch):
+    pr, sv, plan, ctx = _setup(name, oracle)
+    assert plan.N == ctx.N
+    if name in LEVELS:
+        assert plan.N == LEVELS[name]
+    X = _coords(pr)
+    for l in range(plan.L):
+        disp, sig = plan.level_arrays(l)
+        for c in range(pr.dim):
+            d_gpu = disp[c].cpu().numpy()
+            d_ora = (X[c][None, :] - _dep(ctx, pr, l, c)) / pr.h
+            scale = max(1.0, np.abs(d_ora).max())
+            assert np.abs(d_gpu - d_ora).max() < 1e-9 * scale, (l, c)
+            if l > 0:
+                s_gpu, s_ora = sig[c].cpu().numpy(), _sigma(ctx, pr, l, c)
+                assert np.abs(s_gpu - s_ora).max() < 1e-9 * max(1.0, np.abs(s_ora).max()), (l, c)
+    if name.startswith("alpha0") or name.startswith("field0"):
+        # zero velocity: no displacement, and sigma vanishes on every level
+        for l in range(plan.L):
+            disp, sig = plan.level_arrays(l)
+            assert not disp.any()
+            if l > 0:
+                assert not sig.any()
+    if name.startswith("int_cfl"):
+        # constant velocity at CFL 2: every displacement is m^l * 2 (in 2D
+        # the y component -m^l * 2) to rounding
+        for l in range(plan.L):
+            d = plan.level_arrays(l)[0].cpu().numpy()
+            scale = int(np.prod(plan.m[:l])) * 2.0
+            assert np.abs(d[0] - scale).max() < 1e-12 * scale
+            if pr.dim == 2:
+                assert np.abs(d[1] + scale).max() < 1e-12 * scale
+    if name.startswith("wrap_many"):
+        # the largest fine displacement spans more than the periodic mesh
+        assert np.abs(plan.level_arrays(0)[0].cpu().numpy()).max() > pr.nx
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_apply_phi_every_level(name, oracle, torch):
+    pr, sv, plan, ctx = _setup(name, oracle)
+    rng = np.random.default_rng(5)
+    for l in range(plan.L):
+        cnt = min(plan.N[l], 4)
+        n0 = plan.N[l] - cnt
+        xin = rng.standard_normal((cnt, pr.S))
+        out = plan.apply_phi(l, n0, torch.from_numpy(xin)).cpu().numpy()
+        ref = np.stack([ctx.apply_phi(l, n0 + k, xin[k]) for k in range(cnt)])
+        assert _rel(out, ref) < 1e-11, (l, _rel(out, ref))
+        if name.startswith("alpha0") or name.startswith("field0"):
+            # every level's step is the identity
+            assert _rel(out, xin) < 1e-14
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_sequential_stepping(name, oracle, torch):
+    pr, sv, plan, ctx = _setup(name, oracle)
+    u0 = I.initial_condition(pr, 0)
+    u = plan.step(torch.from_numpy(u0)).cpu().numpy()
+    ref = oracle.seq_fine(pr, u0)
+    assert _rel(u, ref) < 1e-11
+    if name.startswith("int_cfl"):
+        # at integer CFL with constant velocity each step is an exact shift
+        # by two nodes (2D: +2 in x, -2 in y), so node values are carried
+        # over to rounding
+        shape = (pr.nx,) if pr.dim == 1 else (pr.nx, pr.nx)
+        exp = u0.reshape(shape)
+        for n in range(1, pr.nt + 1):
+            exp = np.roll(exp, 2, axis=-1)
+            if pr.dim == 2:
+                exp = np.roll(exp, -2, axis=0)
+            assert np.abs(u[n] - exp.reshape(-1)).max() < 1e-13 * np.abs(u0).max(), n
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_mgrit_solve(name, oracle, torch):
+    pr, sv, plan, ctx = _setup(name, oracle)
+    u0 = I.initial_condition(pr, 0)
+    ui = I.initial_iterate(pr.nt, pr.S, plan.m[0] if plan.L > 1 else 1, 1)
+    u_ref, st_ref, h_ref = ctx.mgrit(u0, ui)
+    u = torch.from_numpy(ui).cuda()
+    st, hist = plan.solve(torch.from_numpy(u0), u)
+    assert st["status"] == st_ref["status"]
+    assert st["iterations"] == st_ref["iterations"]
+    assert st["n_levels"] == st_ref["n_levels"] == plan.L
+    if plan.L > 1:
+        assert len(hist) == len(h_ref)
+        assert np.abs(hist - h_ref).max() <= 1e-8 * h_ref[0] + 1e-12 * np.abs(h_ref).max()
+        big = h_ref > 1e-7 * h_ref[0]
+        if big.any():
+            assert np.abs(hist[big] / h_ref[big] - 1).max() < 1e-6
+        assert st["gmres_solves"] == st_ref["gmres_solves"]
+        assert abs(st["gmres_iters"] - st_ref["gmres_iters"]) <= 3 * sv.gmres_kmax
+    uc = u.cpu().numpy()
+    assert _rel(uc, u_ref) < 1e-9
+    # converged MGRIT reproduces sequential stepping
+    assert _rel(uc, oracle.seq_fine(pr, u0)) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["min_nx8_1d", "ragged_coarsest_1d", "min_nx8_2d"])
+def test_zero_data(name, oracle, torch):
+    """u0 = 0 and a zero initial iterate: the first residual is exactly zero,
+    both sides stop after one cycle and the solution stays exactly zero."""
+    pr, sv, plan, ctx = _setup(name, oracle)
+    z0 = np.zeros(pr.S)
+    zi = np.zeros((pr.nt + 1, pr.S))
+    u_ref, st_ref, h_ref = ctx.mgrit(z0, zi)
+    u = torch.zeros(pr.nt + 1, pr.S, dtype=torch.float64, device="cuda")
+    st, hist = plan.solve(torch.from_numpy(z0), u)
+    assert st_ref["rho0"] == 0.0 and st["rho0"] == 0.0
+    assert st["status"] == st_ref["status"] == "converged"
+    assert st["iterations"] == st_ref["iterations"]
+    assert np.array_equal(hist, h_ref)
+    assert not u.any() and not u_ref.any()
+
+
+# ------------------------------------------------------------------ 4096^2
+@pytest.fixture(scope="module")
+def max2d(oracle, torch):
+    from paper_2203_13382_amd import Plan
+    a, b = W.field_cfg3()
+    pr = W.Problem(2, 4096, 8, 2.0 * 2 / 4096, 5, 5, a, b)
+    sv = W.Solver(m=[4], max_levels=2)
+    print("edge case max_2d: nx=4096 nt=8 p=5 m=[4]", flush=True)
+    plan = Plan(pr, sv, "fp64").setup()
+    ctx = oracle.Context(pr, sv)
+    u0 = I.initial_condition(pr, 0)
+    # sequential stepping by the oracle's level-0 step, slice by slice
+    seq = [u0]
+    for n in range(pr.nt):
+        seq.append(ctx.apply_phi(0, n, seq[-1]))
+    return pr, sv, plan, ctx, u0, np.stack(seq)
+
+
+def test_max_2d_setup_and_steps(max2d, torch):
+    pr, sv, plan, ctx, u0, seq = max2d
+    assert plan.N == ctx.N == [8, 2]
+    # the level-0 step runs LDS-tiled at this size
+    assert plan.tile_choice() is not None
+    X = _coords(pr)
+    for l, steps in ((0, (0, pr.nt - 1)), (1, (0, 1))):
+        disp, sig = plan.level_arrays(l)
+        for c in (0, 1):
+            dep = ctx.dep(l, c)
+            for n in steps:
+                ref = (X[c] - dep[n]) / pr.h
+                assert np.abs(disp[c][n].cpu().numpy() - ref).max() < 1e-9 * max(1.0, np.abs(ref).max()), (l, c, n)
+            if l > 0:
+                s_o = ctx.sigma(l, c)
+                assert np.abs(sig[c].cpu().numpy() - s_o).max() < 1e-9 * max(1.0, np.abs(s_o).max()), (l, c)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(pr.S)
+    for l, n in ((0, pr.nt - 1), (1, 1)):
+        out = plan.apply_phi(l, n, torch.from_numpy(x[None, :])).cpu().numpy()[0]
+        assert _rel(out, ctx.apply_phi(l, n, x)) < 1e-11, l
+    u = plan.step(torch.from_numpy(u0)).cpu().numpy()
+    assert _rel(u, seq) < 1e-11
+
+
+def test_max_2d_mgrit_reaches_stepping(max2d, torch):
+    """MGRIT on the largest mesh with 32 steps (levels of 32, 8 and 2 steps,
+    so the solve takes several cycles; with the 2 coarse intervals of the
+    8-step plan FCF relaxation alone makes one cycle exact) converges to the
+    sequential stepping of the same plan, which the test above pins to the
+    oracle.  Residuals fall in every cycle until they reach zero."""
+    from paper_2203_13382_amd import Plan
+    pr8, sv, _, _, u0, _ = max2d
+    pr = W.Problem(2, pr8.nx, 32, pr8.dt, pr8.p, pr8.r, pr8.alpha, pr8.beta)
+    plan = Plan(pr, W.Solver(m=[4]), "fp64").setup()
+    assert plan.N == [32, 8, 2]
+    tu0 = torch.from_numpy(u0)
+    useq = plan.step(tu0)
+    u = torch.zeros(pr.nt + 1, pr.S, dtype=torch.float64, device="cuda")
+    plan.seed_iterate(u, 1)
+    st, hist = plan.solve(tu0, u)
+    print(f"max_2d MGRIT: {st['iterations']} cycles, rho {st['rho0']:.3e} -> {st['rho_final']:.3e}")
+    assert st["status"] == "converged" and st["iterations"] > 1
+    assert st["rho_final"] <= sv.tol * st["rho0"]
+    h = np.append(hist, st["rho_final"])
+    assert all(h[k + 1] < h[k] or h[k + 1] == 0.0 for k in range(len(h) - 1)), h
+    err = ((u - useq).abs().max() / useq.abs().max()).item()
+    assert err < 1e-8, err
+
+
+def test_max_2d_fp32_bulk(max2d, torch):
+    """FP32 bulk at the largest mesh: stepping agrees with the FP64 oracle to
+    FP32 accuracy (8 steps, each rounding to about 6e-8 relative).  The bound
+    is about three times the 1.25e-6 measured on MI355X."""
+    from paper_2203_13382_amd import Plan
+    pr, sv, plan, ctx, u0, seq = max2d
+    p32 = Plan(pr, sv, "fp32").setup()
+    u = p32.step(torch.from_numpy(u0.astype(np.float32))).cpu().numpy()
+    err = _rel(u.astype(np.float64), seq)
+    print(f"max_2d fp32 stepping: rel. error {err:.2e}")
+    assert err < 4e-6
