@@ -45,8 +45,8 @@ __device__ __forceinline__ T interp2(const T *__restrict__ s, int i, int j, TD d
     const int bx = wrap_mod(i - int(fx) + firstx, nx);
     const int by = wrap_mod(j - int(fy) + firsty, nx);
     T wx[P + 1], wy[P + 1];
-    lagrange_weights<P, T>(-ex - T(firstx), wx);
-    lagrange_weights<P, T>(-ey - T(firsty), wy);
+    interp_weights<P, T>(ex, wx);
+    interp_weights<P, T>(ey, wy);
     T acc = T(0);
 #pragma unroll
     for (int b = 0; b <= P; ++b) {
@@ -146,8 +146,8 @@ __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ 
         T v;
         if (bx >= 0 && by >= 0 && bx + P < wx && by + P < wy) {
             T wxv[P + 1], wyv[P + 1];
-            lagrange_weights<P, T>(-ex - T(firstx), wxv);
-            lagrange_weights<P, T>(-ey - T(firsty), wyv);
+            interp_weights<P, T>(ex, wxv);
+            interp_weights<P, T>(ey, wyv);
             T acc = T(0);
 #pragma unroll
             for (int b = 0; b <= P; ++b) {
@@ -281,8 +281,8 @@ __global__ void __launch_bounds__(TPB) step2d_win_kernel(const T *__restrict__ s
             const int w = (int)bw;
             const int bx = gx[k] - xlo, by = gy[k] - ylo;
             T wxv[P + 1], wyv[P + 1];
-            lagrange_weights<P, T>(-ex[k] - T(stencil_first<T>(P, ex[k])), wxv);
-            lagrange_weights<P, T>(-ey[k] - T(stencil_first<T>(P, ey[k])), wyv);
+            interp_weights<P, T>(ex[k], wxv);
+            interp_weights<P, T>(ey[k], wyv);
             T acc = T(0);
 #pragma unroll
             for (int b = 0; b <= P; ++b) {

@@ -101,6 +101,55 @@ __device__ __forceinline__ void lagrange_weights(F z, F (&w)[P + 1])
     }
 }
 
+// Weights of the interpolation stencil at the departure point, from eps
+// (w[j] for the node first+j, first = stencil_first(P, eps)): the same
+// Lagrange polynomials as lagrange_weights(-eps - first), evaluated in fewer
+// operations for odd p.  There the p+1 nodes sit symmetrically about the
+// midpoint of the departure cell; with s the departure point's offset from
+// that midpoint (s = 1/2 - eps, in cells) and Q = s^2, node pairs +-c give
+// the factor (s - c)(s + c) = Q - c^2, so every weight is a product of such
+// factors times one linear factor:
+//   p = 3 (nodes at s = -3/2, -1/2, 1/2, 3/2):
+//     w = { -a (s - 3/2), b (s - 1/2), -b (s + 1/2), a (s + 3/2) },
+//     a = (Q - 1/4) / 6, b = (Q - 9/4) / 2;
+//   p = 5 (nodes at s = -5/2 .. 5/2):
+//     w = { -a (s - 5/2), b (s - 3/2), -c (s - 1/2), c (s + 1/2), -b (s + 3/2), a (s + 5/2) },
+//     a = (Q - 9/4)(Q - 1/4) / 120, b = (Q - 25/4)(Q - 1/4) / 24, c = (Q - 25/4)(Q - 9/4) / 12;
+//   p = 1: w = { eps, 1 - eps }.
+// Even p keeps the general product form.
+template <int P, typename F>
+__device__ __forceinline__ void interp_weights(F eps, F (&w)[P + 1])
+{
+    if constexpr (P == 1) {
+        w[0] = eps;
+        w[1] = F(1) - eps;
+    } else if constexpr (P == 3) {
+        const F s = F(0.5) - eps, q = s * s;
+        const F a = fma(q, F(1.0 / 6.0), F(-1.0 / 24.0));
+        const F b = fma(q, F(0.5), F(-1.125));
+        const F a3 = F(1.5) * a, b1 = F(0.5) * b;
+        w[0] = fma(-a, s, a3);
+        w[1] = fma(b, s, -b1);
+        w[2] = fma(-b, s, -b1);
+        w[3] = fma(a, s, a3);
+    } else if constexpr (P == 5) {
+        const F s = F(0.5) - eps, q = s * s;
+        const F p25 = q - F(6.25);
+        const F p15 = fma(q, F(1.0 / 12.0), F(-2.25 / 12.0));     // (Q - 9/4) / 12
+        const F p05 = fma(q, F(1.0 / 24.0), F(-0.25 / 24.0));     // (Q - 1/4) / 24
+        const F c = p25 * p15, b = p25 * p05, a = F(2.4) * (p15 * p05);
+        const F a5 = F(2.5) * a, b3 = F(1.5) * b, c1 = F(0.5) * c;
+        w[0] = fma(-a, s, a5);
+        w[1] = fma(b, s, -b3);
+        w[2] = fma(-c, s, c1);
+        w[3] = fma(c, s, c1);
+        w[4] = fma(-b, s, -b3);
+        w[5] = fma(a, s, a5);
+    } else {
+        lagrange_weights<P, F>(-eps - F(stencil_first<F>(P, eps)), w);
+    }
+}
+
 // f_{p+1}(z) of eq. (fpoly_def), odd p: (1/(p+1)!) prod_{q=-l}^{r} (q + z).
 __device__ __forceinline__ double fpoly_odd(int p, double z)
 {

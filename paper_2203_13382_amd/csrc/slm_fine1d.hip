@@ -46,10 +46,16 @@ hipError_t fine_ept(const ChainArgs &a, int nchains, hipStream_t st)
         if (b <= SLM_MAXB) block = b;
     }
     const int ept = (a.nx + block - 1) / block;
-    const size_t lds = (((size_t)(DBUF ? 2 : 1) * fine_slice_len(a.nx) * sizeof(T) + 15) & ~size_t(15)) +
-                       SLM_RED_DOUBLES * sizeof(double);
-#define FL(E) (a.nx == (E) * block ? launch(fine1d<T, TD, P, E, DBUF, pf_depth<TD, E>(), true>, nchains, block, lds, a, st) \
-                                   : launch(fine1d<T, TD, P, E, DBUF, pf_depth<TD, E>(), false>, nchains, block, lds, a, st))
+    // the fast variant: the slice fills the workgroup and the displacement
+    // bound gives a pad that the threads of one row can write
+    const bool fast_ok = a.fpad > 0 && a.fpad <= block;
+    auto lds_for = [&](bool fast) {
+        const size_t slen = fast ? fast_slice_len(a.nx, a.fpad) : fine_slice_len(a.nx);
+        return (((size_t)(DBUF ? 2 : 1) * slen * sizeof(T) + 15) & ~size_t(15)) + SLM_RED_DOUBLES * sizeof(double);
+    };
+#define FL(E) (fast_ok && a.nx == (E) * block                                                                      \
+                   ? launch(fine1d<T, TD, P, E, DBUF, pf_depth<TD, E>(), true>, nchains, block, lds_for(true), a, st) \
+                   : launch(fine1d<T, TD, P, E, DBUF, pf_depth<TD, E>(), false>, nchains, block, lds_for(false), a, st))
     switch (ept) {
     case 1: return FL(1);
     case 2: return FL(2);
@@ -83,7 +89,9 @@ hipError_t launch_fine_1d(int nchains, bool f32, const ChainArgs &a, hipStream_t
     // the extra barrier per step (level-0 sweep of the 1D workload: 152 ->
     // 142 us).
     const size_t extra = SLM_RED_DOUBLES * sizeof(double) + 16;
-    const bool fits = 2ull * fine_slice_len(a.nx) * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
+    const size_t slen = a.fpad > 0 && fast_slice_len(a.nx, a.fpad) > fine_slice_len(a.nx) ? fast_slice_len(a.nx, a.fpad)
+                                                                                            : fine_slice_len(a.nx);
+    const bool fits = 2ull * slen * (f32 ? 4 : 8) + extra <= (size_t)lds_limit();
     bool dbuf = fits && (f32 || nchains < 512);
     if (a.dbuf_hint >= 0 && !a.R && nchains >= 64) dbuf = fits && a.dbuf_hint;
     if (f32) return dbuf ? fine_p<float, float, true>(a, nchains, st) : fine_p<float, float, false>(a, nchains, st);

@@ -90,6 +90,8 @@ struct ChainArgs {
     double rtol;
     unsigned long long *counter;
     int nsmall;              // |displacement| bound < nx - p - 1 (cheap wrap)
+    int fpad;                // level 0: periodic copies on each side of the fast sweep's LDS slice
+                             // (ceil(|displacement| bound) + p + 2; 0: no padded variant)
     int adj;                 // 1: adjoint system in reverse time (transposed steps)
     int Nl;                  // level steps; step n of the adjoint uses forward step Nl-1-n
     int fwd;                 // coarse level with the explicit forward-Euler operator (eq. Fp_def)

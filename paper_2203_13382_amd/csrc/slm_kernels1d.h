@@ -25,7 +25,10 @@ __host__ __device__ inline int fine_block(int nx, long long nchains)
 
 // Interpolate the LDS slice `s` at the departure point of node i whose
 // displacement is d cells (xi = x_i - d h): x_E = x_{i - floor(d)},
-// eps = d - floor(d) (eq. depart_decompose).
+// eps = d - floor(d) (eq. depart_decompose).  The coarse-level kernels call
+// this one; it keeps the general product form of the weights, which needs
+// fewer live registers than interp_weights in kernels that hold a Krylov
+// basis in registers.
 template <int P, typename T, typename TD>
 __device__ __forceinline__ T interp1(const T *__restrict__ s, int i, TD d, int nx, int nsmall)
 {
@@ -58,7 +61,8 @@ constexpr int SLM_SLICE_PAD = 8;
 __host__ __device__ inline size_t fine_slice_len(int nx) { return (size_t)nx + SLM_SLICE_PAD; }
 
 // interp1 on a padded slice: one wrap of the stencil start, then p+1
-// consecutive LDS reads (same products and summation order as interp1).
+// consecutive LDS reads (same products and summation order as
+// interp1_nowrap, so every level-0 variant rounds alike).
 template <int P, typename T, typename TD>
 __device__ __forceinline__ T interp1_padded(const T *__restrict__ s, int i, TD d, int nx, int nsmall)
 {
@@ -74,7 +78,7 @@ __device__ __forceinline__ T interp1_padded(const T *__restrict__ s, int i, TD d
         base = wrap_mod(base, nx);
     }
     T w[P + 1];
-    lagrange_weights<P, T>(-eps - T(first), w);
+    interp_weights<P, T>(eps, w);
     const T *sp = s + base;
     T acc = T(0);
 #pragma unroll
@@ -90,6 +94,39 @@ __device__ __forceinline__ void pad_slice(T *sl, T v0, int nx)
     const int tid = threadIdx.x;
     if (tid < nx)
         for (int t = tid; t < SLM_SLICE_PAD; t += nx) sl[nx + t] = v0;
+}
+
+// The fast level-0 sweep (nx = EPT * blockDim) keeps fpad periodic copies on
+// each side of its LDS slice: sl[-fpad .. -1] repeat nodes nx-fpad .. nx-1
+// and sl[nx .. nx+fpad-1] nodes 0 .. fpad-1.  With fpad >= ceil(|d|) + p + 2
+// every stencil start i - floor(d) + first lies in [-fpad, nx+fpad-p-1], so
+// the taps are read with no wrap at all (same products and summation order
+// as interp1_padded).
+__host__ __device__ inline size_t fast_slice_len(int nx, int fpad) { return (size_t)nx + 2 * (size_t)fpad; }
+
+template <int P, typename T, typename TD>
+__device__ __forceinline__ T interp1_nowrap(const T *__restrict__ s, int i, TD d)
+{
+    const TD fl = floor(d);
+    const T eps = T(d - fl);
+    T w[P + 1];
+    interp_weights<P, T>(eps, w);
+    const T *sp = s + (i - int(fl) + stencil_first<T>(P, eps));
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j <= P; ++j) acc += w[j] * sp[j];
+    return acc;
+}
+
+// Both pads of a fast slice from the strided registers: thread t holds node
+// t in val[0] and node (EPT-1) * blockDim + t = nx - blockDim + t in
+// val[EPT-1]; fpad <= blockDim.
+template <typename T, int EPT>
+__device__ __forceinline__ void pad_fast(T *sl, const T (&val)[EPT], int nx, int fpad)
+{
+    const int tid = threadIdx.x, B = blockDim.x;
+    if (tid < fpad) sl[nx + tid] = val[0];
+    if (tid >= B - fpad) sl[tid - B] = val[EPT - 1];
 }
 
 // Load the chain's start slice into LDS (and registers); optionally copy it
@@ -164,17 +201,19 @@ __device__ __forceinline__ void chain_finish(const ChainArgs &a, int j, const T 
 }
 
 // ------------------------------------------------------------------ level 0 (and sequential stepping)
-// FAST: nx == EPT * blockDim and a.nsmall (no node guards, one-sided stencil
-// wrap decided at compile time).
+// FAST: nx == EPT * blockDim and 0 < a.fpad <= blockDim (no node guards; the
+// slice carries periodic pads on both sides, so no stencil wraps).
 template <typename T, typename TD, int P, int EPT, bool DBUF, int PF, bool FAST = false>
 __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned char *smem)
 {
     constexpr bool FULL = FAST;
     const int tid = threadIdx.x, B = blockDim.x, nx = a.nx;
     const long long S = a.S;
-    T *sl0 = reinterpret_cast<T *>(smem);
-    T *sl1 = DBUF ? sl0 + fine_slice_len(nx) : sl0;
-    const size_t off = ((size_t)(DBUF ? 2 : 1) * fine_slice_len(nx) * sizeof(T) + 15) & ~size_t(15);
+    const int lp = FAST ? a.fpad : 0;
+    const size_t slen = FAST ? fast_slice_len(nx, lp) : fine_slice_len(nx);
+    T *sl0 = reinterpret_cast<T *>(smem) + lp;
+    T *sl1 = DBUF ? sl0 + slen : sl0;
+    const size_t off = ((size_t)(DBUF ? 2 : 1) * slen * sizeof(T) + 15) & ~size_t(15);
     double *red = reinterpret_cast<double *>(smem + off);
     const TD *disp = static_cast<const TD *>(a.disp);
     const T *G = static_cast<const T *>(a.G);
@@ -184,7 +223,10 @@ __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned c
 
     T val[EPT];
     chain_start<T, EPT>(a, j, sl0, val, n_first);
-    pad_slice(sl0, val[0], nx);
+    if constexpr (FAST)
+        pad_fast<T, EPT>(sl0, val, nx, lp);
+    else
+        pad_slice(sl0, val[0], nx);
     TD ring[PF][EPT];                           // displacements of the next PF steps
 #pragma unroll
     for (int u = 0; u < PF; ++u)
@@ -218,7 +260,10 @@ __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned c
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int i = tid + e * B;
-                val[e] = (FULL || i < nx) ? interp1_padded<P, T, TD>(src, i, ring[u][e], nx, FAST ? 1 : a.nsmall) : T(0);
+                if constexpr (FAST)
+                    val[e] = interp1_nowrap<P, T, TD>(src, i, ring[u][e]);
+                else
+                    val[e] = i < nx ? interp1_padded<P, T, TD>(src, i, ring[u][e], nx, a.nsmall) : T(0);
                 ring[u][e] = nxt[e];
             }
             if constexpr (!DBUF) __syncthreads();
@@ -235,7 +280,10 @@ __device__ __forceinline__ void fine_chain(const ChainArgs &a, int j, unsigned c
                     if (vrow) vrow[i] = val[e];
                 }
             }
-            pad_slice(dst, val[0], nx);
+            if constexpr (FAST)
+                pad_fast<T, EPT>(dst, val, nx, lp);
+            else
+                pad_slice(dst, val[0], nx);
             if (DBUF) cur ^= 1;
             __syncthreads();
         }

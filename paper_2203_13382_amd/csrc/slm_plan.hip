@@ -73,6 +73,10 @@ ChainArgs base_args(const slm_plan &P, int level)
     a.rtol = P.d.gmres_rtol;
     a.counter = (unsigned long long *)ws_at(P, P.counter);
     a.nsmall = level == 0 && disp_bound(P) + P.d.p + 8 < P.d.nx ? 1 : 0;
+    if (level == 0) {
+        const double f = std::ceil(disp_bound(P)) + P.d.p + 2;
+        a.fpad = f < P.d.nx ? (int)f : 0;
+    }
     a.adj = P.adj_mode;
     a.Nl = P.lv[level].N;
     a.fwd = level > 0 && P.d.coarse_op == SLM_COARSE_FWD_EULER ? 1 : 0;

@@ -4,7 +4,8 @@ FP64 oracle, through the C ABI.
 * the smallest meshes (nx = 8, in 1D and 2D) with the deepest hierarchy m = 2
   allows;
 * departure points that wrap the periodic mesh several times (CFL well
-  above nx), the plain-gather path of both dimensions;
+  above nx): the plain-gather path of both dimensions, and 1D slices that
+  fill a workgroup, at level 0 and on rediscretized coarse levels;
 * hierarchies that stop early: nt = 1 and nt not divisible by m (one level,
   sequential stepping), m = nt (one coarse step), a coarsest level whose
   step count is not a multiple of m;
@@ -37,6 +38,12 @@ def _case(name):
         "ragged_coarsest_1d": (W.Problem(1, 128, 24, 1.5 * 2 / 128, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
         "alpha0_1d": (W.Problem(1, 64, 64, 0.85 * 2 / 64, 3, 3, [W.term(0.0)]), W.Solver(m=[4])),
         "int_cfl_1d": (W.Problem(1, 64, 64, 2 * 2 / 64, 5, 5, [W.term(1.0)]), W.Solver(m=[4])),
+        # nx a multiple of 64 (the slice fills a workgroup) with departure
+        # points more than a period away: at level 0, and on the coarse levels
+        # of the rediscretized operator, whose steps run the level-0 kernel
+        "wrap_fill_1d": (W.Problem(1, 64, 32, 50.0 * 2 / 64, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
+        "redisc_fill_1d": (W.Problem(1, 128, 256, 3.0 * 2 / 128, 3, 3, W.alpha_cfg12()),
+                           W.Solver(m=[4], coarse_op="redisc")),
         "min_nx8_2d": (W.Problem(2, 8, 8, 0.5 * 2 / 8, 3, 3, a3, b3), W.Solver(m=[2])),
         "wrap_many_2d": (W.Problem(2, 16, 16, 20.0 * 2 / 16, 3, 3, [W.term(1.0), W.term(0.3, ky=1.0, kt=1.0)],
                                    [W.term(-1.0), W.term(0.3, kx=1.0)]), W.Solver(m=[4])),
@@ -47,7 +54,7 @@ def _case(name):
 
 
 CASES = ["min_nx8_1d", "wrap_many_1d", "nt1_1d", "nt17_1d", "m_eq_nt_1d", "ragged_coarsest_1d", "alpha0_1d",
-         "int_cfl_1d", "min_nx8_2d", "wrap_many_2d", "field0_2d", "int_cfl_2d"]
+         "int_cfl_1d", "wrap_fill_1d", "redisc_fill_1d", "min_nx8_2d", "wrap_many_2d", "field0_2d", "int_cfl_2d"]
 
 # the level hierarchy each case must build (number of steps per level)
 LEVELS = {"min_nx8_1d": [16, 8, 4, 2, 1], "nt1_1d": [1], "nt17_1d": [17], "m_eq_nt_1d": [16, 1],
@@ -108,7 +115,7 @@ def test_setup_arrays(name, oracle, torch):
             d_ora = (X[c][None, :] - _dep(ctx, pr, l, c)) / pr.h
             scale = max(1.0, np.abs(d_ora).max())
             assert np.abs(d_gpu - d_ora).max() < 1e-9 * scale, (l, c)
-            if l > 0:
+            if l > 0 and sv.coarse_op == "modified":
                 s_gpu, s_ora = sig[c].cpu().numpy(), _sigma(ctx, pr, l, c)
                 assert np.abs(s_gpu - s_ora).max() < 1e-9 * max(1.0, np.abs(s_ora).max()), (l, c)
     if name.startswith("alpha0") or name.startswith("field0"):
@@ -127,9 +134,11 @@ def test_setup_arrays(name, oracle, torch):
             assert np.abs(d[0] - scale).max() < 1e-12 * scale
             if pr.dim == 2:
                 assert np.abs(d[1] + scale).max() < 1e-12 * scale
-    if name.startswith("wrap_many"):
+    if name.startswith("wrap"):
         # the largest fine displacement spans more than the periodic mesh
         assert np.abs(plan.level_arrays(0)[0].cpu().numpy()).max() > pr.nx
+    if name == "redisc_fill_1d":
+        assert np.abs(plan.level_arrays(3)[0].cpu().numpy()).max() > pr.nx
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -142,7 +151,12 @@ def test_apply_phi_every_level(name, oracle, torch):
         xin = rng.standard_normal((cnt, pr.S))
         out = plan.apply_phi(l, n0, torch.from_numpy(xin)).cpu().numpy()
         ref = np.stack([ctx.apply_phi(l, n0 + k, xin[k]) for k in range(cnt)])
-        assert _rel(out, ref) < 1e-11, (l, _rel(out, ref))
+        # eps = d - floor(d) carries an absolute rounding error of about
+        # |d| * 2^-52 on either side, which the interpolant of random data
+        # amplifies by its slope in eps (order 10-30 x max|x|): a relative
+        # 1e-13 per cell of displacement on top of the rounding of the step
+        dmax = float(plan.level_arrays(l)[0].abs().max())
+        assert _rel(out, ref) < 1e-11 + 1e-13 * dmax, (l, dmax, _rel(out, ref))
         if name.startswith("alpha0") or name.startswith("field0"):
             # every level's step is the identity
             assert _rel(out, xin) < 1e-14
