@@ -102,7 +102,7 @@ struct TileShape { int tx, ty; };
 constexpr TileShape kTiles[] = {{64, 16}, {64, 32}, {128, 16}, {128, 32}};
 constexpr int kNumTiles = 4;
 
-template <typename T, typename TD, int P, int TX, int TY>
+template <typename T, typename TD, int P, int TX, int TY, bool PRE>
 __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ src, long long src_stride,
                                                           T *__restrict__ dst, long long dst_stride,
                                                           const TD *__restrict__ disp, long long plane, int nx,
@@ -120,6 +120,25 @@ __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ 
     const int x0 = (int)(blockIdx.x % ntx) * TX, y0 = (int)(blockIdx.x / ntx) * TY;
     const int wx = TX + 2 * F + LO + HI, wy = TY + 2 * F + LO + HI;
     const int ox = x0 - F - LO, oy = y0 - F - LO;   // window origin (unwrapped)
+    // PRE (launches of a few hundred workgroups, e.g. sequential stepping,
+    // where each CU waits on its own loads): this thread's outputs are nodes
+    // threadIdx.x + u * TPB of the tile, and their displacements are
+    // requested before the window is staged so the loads overlap it.  Big
+    // sweeps keep the registers for occupancy instead.
+    constexpr int NPT = TX * TY / TPB;
+    static_assert(TX * TY % TPB == 0, "a tile is a whole number of workgroup rows");
+    TD dxr[NPT], dyr[NPT];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int k = threadIdx.x + u * TPB, ly = k / TX, lx = k - ly * TX;
+            const int i = x0 + lx, j = y0 + ly;
+            const long long id = (long long)j * nx + i;
+            const bool in = i < nx && j < nx;
+            dxr[u] = in ? disp[n * S + id] : TD(0);
+            dyr[u] = in ? disp[plane + n * S + id] : TD(0);
+        }
+    }
     // Every window coordinate lies in (-nx, 2 nx) (checked on the host), so
     // one conditional add or subtract wraps it; k / wx is a multiply by a
     // 24-bit reciprocal, exact for k < wx * wy.
@@ -133,12 +152,11 @@ __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ 
         win[k] = s[(long long)gy * nx + gx];
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < TX * TY; k += TPB) {
+    // output k of the tile from its displacement (dx, dy)
+    auto output = [&](int k, TD dx, TD dy) {
         const int ly = k / TX, lx = k - ly * TX;
         const int i = x0 + lx, j = y0 + ly;
-        if (i >= nx || j >= nx) continue;
         const long long id = (long long)j * nx + i;
-        const TD dx = disp[n * S + id], dy = disp[plane + n * S + id];
         const TD fx = floor(dx), fy = floor(dy);
         const T ex = T(dx - fx), ey = T(dy - fy);
         const int firstx = stencil_first<T>(P, ex), firsty = stencil_first<T>(P, ey);
@@ -164,6 +182,25 @@ __global__ void __launch_bounds__(TPB) step2d_tile_kernel(const T *__restrict__ 
         if (G) v += G[(n + 1) * S + id];
         dst[c * dst_stride + id] = v;
         if (Vout) Vout[(n + 1) * S + id] = v;
+    };
+    if constexpr (PRE) {
+        // opaque thread index: the output addresses are formed again here
+        // rather than kept live from the loads above
+        int t = threadIdx.x;
+        __asm__ volatile("" : "+v"(t));
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int k = t + u * TPB, ly = k / TX, lx = k - ly * TX;
+            if (x0 + lx < nx && y0 + ly < nx) output(k, dxr[u], dyr[u]);
+        }
+    } else {
+        for (int k = threadIdx.x; k < TX * TY; k += TPB) {
+            const int ly = k / TX, lx = k - ly * TX;
+            const int i = x0 + lx, j = y0 + ly;
+            if (i >= nx || j >= nx) continue;
+            const long long id = (long long)j * nx + i;
+            output(k, disp[n * S + id], disp[plane + n * S + id]);
+        }
     }
 }
 
@@ -831,8 +868,15 @@ hipError_t launch_step0(const slm_plan &P, int nch, hipStream_t st, const T *src
     const TileShape ts = kTiles[tile];
     const dim3 grid(((nx + ts.tx - 1) / ts.tx) * ((nx + ts.ty - 1) / ts.ty), nch);
     const unsigned inv_wx = (unsigned)(((1u << 24) + wx - 1) / wx);     // ceil(2^24 / wx)
-#define STEPT(PP, TXX, TYY) hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP, TXX, TYY>), grid, dim3(TPB), lds, st, src, \
-                                               ss, dst, ds, disp, plane, nx, n_first, stride, G, Vout, F, inv_wx)
+    // small launches prefetch each thread's displacements (see the kernel)
+    const bool pre = (long long)grid.x * grid.y < 1024;
+#define STEPT(PP, TXX, TYY)                                                                                         \
+    if (pre)                                                                                                        \
+        hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP, TXX, TYY, true>), grid, dim3(TPB), lds, st, src, ss, dst,  \
+                           ds, disp, plane, nx, n_first, stride, G, Vout, F, inv_wx);                                \
+    else                                                                                                            \
+        hipLaunchKernelGGL((step2d_tile_kernel<T, TD, PP, TXX, TYY, false>), grid, dim3(TPB), lds, st, src, ss, dst, \
+                           ds, disp, plane, nx, n_first, stride, G, Vout, F, inv_wx)
 #define STEPP(TXX, TYY)                                       \
     switch (p) {                                              \
     case 1: STEPT(1, TXX, TYY); break;                        \
@@ -957,13 +1001,10 @@ hipError_t chain_batch(const slm_plan &P, int level, const ChainArgs &a, int c0,
                                            (const T *)a.G, vo);
             if (e != hipSuccess) return e;
         } else if (level == 0) {
-            if (P.d.precision == SLM_FP32_BULK)
-                e = launch_step0<T, float>(P, nch, st, bufs[cur], S, bufs[cur ^ 1], S, (const float *)ws_at(P, L.disp),
-                                           plane, n_first0 + k, a.stride_chain, (const T *)a.G, vo);
-            else
-                e = launch_step0<T, double>(P, nch, st, bufs[cur], S, bufs[cur ^ 1], S,
-                                            (const double *)ws_at(P, L.disp), plane, n_first0 + k, a.stride_chain,
-                                            (const T *)a.G, vo);
+            // level-0 displacements have the bulk type (FP32 bulk is T = float)
+            if ((P.d.precision == SLM_FP32_BULK) != std::is_same<T, float>::value) return hipErrorInvalidValue;
+            e = launch_step0<T, T>(P, nch, st, bufs[cur], S, bufs[cur ^ 1], S, (const T *)ws_at(P, L.disp), plane,
+                                   n_first0 + k, a.stride_chain, (const T *)a.G, vo);
             if (e != hipSuccess) return e;
         } else {
             // forward: interpolation into the GMRES right-hand side; adjoint:
