@@ -44,6 +44,9 @@ def _case(name):
         "wrap_fill_1d": (W.Problem(1, 64, 32, 50.0 * 2 / 64, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
         "redisc_fill_1d": (W.Problem(1, 128, 256, 3.0 * 2 / 128, 3, 3, W.alpha_cfg12()),
                            W.Solver(m=[4], coarse_op="redisc")),
+        # the widest periodic pad of the fast level-0 slice: bound 57.5 cells
+        # on 64 nodes gives ceil(57.5) + p + 2 = 63 = nx - 1 copies per side
+        "pad_max_1d": (W.Problem(1, 64, 32, (57.5 / 1.5) * 2 / 64, 3, 3, W.alpha_cfg12()), W.Solver(m=[4])),
         "min_nx8_2d": (W.Problem(2, 8, 8, 0.5 * 2 / 8, 3, 3, a3, b3), W.Solver(m=[2])),
         "wrap_many_2d": (W.Problem(2, 16, 16, 20.0 * 2 / 16, 3, 3, [W.term(1.0), W.term(0.3, ky=1.0, kt=1.0)],
                                    [W.term(-1.0), W.term(0.3, kx=1.0)]), W.Solver(m=[4])),
@@ -54,7 +57,7 @@ def _case(name):
 
 
 CASES = ["min_nx8_1d", "wrap_many_1d", "nt1_1d", "nt17_1d", "m_eq_nt_1d", "ragged_coarsest_1d", "alpha0_1d",
-         "int_cfl_1d", "wrap_fill_1d", "redisc_fill_1d", "min_nx8_2d", "wrap_many_2d", "field0_2d", "int_cfl_2d"]
+         "int_cfl_1d", "wrap_fill_1d", "redisc_fill_1d", "pad_max_1d", "min_nx8_2d", "wrap_many_2d", "field0_2d", "int_cfl_2d"]
 
 # the level hierarchy each case must build (number of steps per level)
 LEVELS = {"min_nx8_1d": [16, 8, 4, 2, 1], "nt1_1d": [1], "nt17_1d": [17], "m_eq_nt_1d": [16, 1],
@@ -205,6 +208,18 @@ def test_mgrit_solve(name, oracle, torch):
     assert _rel(uc, u_ref) < 1e-9
     # converged MGRIT reproduces sequential stepping
     assert _rel(uc, oracle.seq_fine(pr, u0)) < 1e-8
+
+
+def test_pad_max_fp32_stepping(oracle, torch):
+    """The FP32 level-0 kernel with the widest pad agrees with the FP64 oracle
+    to FP32 accuracy (32 steps of about 6e-8 each)."""
+    from paper_2203_13382_amd import Plan
+    pr, sv = _case("pad_max_1d")
+    u0 = I.initial_condition(pr, 0)
+    u = Plan(pr, sv, "fp32").setup().step(torch.from_numpy(u0.astype(np.float32))).cpu().numpy()
+    err = _rel(u.astype(np.float64), oracle.seq_fine(pr, u0))
+    print(f"pad_max fp32 stepping: rel. error {err:.2e}")
+    assert err < 1e-5
 
 
 @pytest.mark.parametrize("name", ["min_nx8_1d", "ragged_coarsest_1d", "min_nx8_2d"])
