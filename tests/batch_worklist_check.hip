@@ -11,6 +11,12 @@
 #include "slm_batch.hip"
 #include <cstdio>
 
+// findings are printed only when asked (verbose)
+#define REPORT(...) \
+    do {                \
+        if (verbose) printf(__VA_ARGS__); \
+    } while (0)
+
 extern "C" int check_batch(void *handle, int verbose, long long shrink)
 {
     slm_batch *B = (slm_batch *)handle;
@@ -31,14 +37,14 @@ extern "C" int check_batch(void *handle, int verbose, long long shrink)
             };
             std::vector<slm_batch::Op> ops;
             const size_t bytes = bd.finish(B->o_items, B->blob, ops);
-            if (bytes > B->items_cap) { printf("items %zu > cap %zu\n", bytes, B->items_cap); ++bad; }
+            if (bytes > B->items_cap) { REPORT("items %zu > cap %zu\n", bytes, B->items_cap); ++bad; }
             auto inside = [&](const slm_plan &P, const void *p, size_t lo, size_t hi, const char *what, int it) {
                 if (!p) return;
                 const char *c = (const char *)p;
                 const size_t cap = (&P == B->plans[0] && shrink > 0) ? top0 - (size_t)shrink : P.ws_bytes;
                 if (c + lo < P.ws || c + hi > P.ws + cap) {
                     if (bad < 20)
-                        printf("item %d %s out of plan ws: [%lld, %lld) of %zu\n", it, what,
+                        REPORT("item %d %s out of plan ws: [%lld, %lld) of %zu\n", it, what,
                                (long long)(c + lo - P.ws), (long long)(c + hi - P.ws), cap);
                     ++bad;
                 }
@@ -61,9 +67,9 @@ extern "C" int check_batch(void *handle, int verbose, long long shrink)
                 int lev = -1;
                 for (int l = 0; l < P.L; ++l)
                     if ((const char *)a.disp == ws_at(P, P.lv[l].disp)) lev = l;
-                if (lev < 0) { printf("item %zu: disp matches no level\n", k); ++bad; continue; }
+                if (lev < 0) { REPORT("item %zu: disp matches no level\n", k); ++bad; continue; }
                 const size_t TD = (lev == 0 && B->fp32) ? 4 : 8;
-                if (nf < 0 || nf + a.nsteps > P.lv[lev].N) { printf("item %zu: steps [%lld,%lld) of N=%d\n", k, nf, nf + a.nsteps, P.lv[lev].N); ++bad; }
+                if (nf < 0 || nf + a.nsteps > P.lv[lev].N) { REPORT("item %zu: steps [%lld,%lld) of N=%d\n", k, nf, nf + a.nsteps, P.lv[lev].N); ++bad; }
                 inside(P, a.disp, nf * S * TD, (nf + a.nsteps) * S * TD, "disp", (int)k);
                 inside(P, a.sigma, nf * S * 8, (nf + a.nsteps) * S * 8, "sigma", (int)k);
                 inside(P, a.G, (nf + 1) * S * T, (nf + a.nsteps + 1) * S * T, "G", (int)k);
@@ -74,21 +80,21 @@ extern "C" int check_batch(void *handle, int verbose, long long shrink)
                 inside(P, a.R, (size_t)(j + 1) * S * T, (size_t)(j + 2) * S * T, "R", (int)k);
                 inside(P, a.partial, (size_t)j * 8, (size_t)(j + 1) * 8, "partial", (int)k);
                 inside(P, a.counter, 0, 16, "counter", (int)k);
-                if (a.nx != P.d.nx || a.S != P.S || a.p != P.d.p) { printf("item %zu: shape mismatch\n", k); ++bad; }
+                if (a.nx != P.d.nx || a.S != P.S || a.p != P.d.p) { REPORT("item %zu: shape mismatch\n", k); ++bad; }
             }
             for (size_t k = 0; k < bd.copies.size(); ++k) {
                 const BCopy &c = bd.copies[k];
                 const char *wsb = B->ws, *wse = B->ws + B->ws_bytes;
                 const size_t ext_d = ((size_t)(c.count - 1) * c.ds + c.S) * T, ext_s = ((size_t)(c.count - 1) * c.ss + c.S) * T;
-                if (c.dst && ((const char *)c.dst < wsb || (const char *)c.dst + ext_d > wse)) { printf("copy %zu dst out\n", k); ++bad; }
-                if (c.src && ((const char *)c.src < wsb || (const char *)c.src + ext_s > wse)) { printf("copy %zu src out\n", k); ++bad; }
+                if (c.dst && ((const char *)c.dst < wsb || (const char *)c.dst + ext_d > wse)) { REPORT("copy %zu dst out\n", k); ++bad; }
+                if (c.src && ((const char *)c.src < wsb || (const char *)c.src + ext_s > wse)) { REPORT("copy %zu src out\n", k); ++bad; }
             }
             // ops: items and descriptors inside the item region
             for (const auto &o : ops) {
-                if (o.kind <= 1 && o.off + (size_t)o.n * sizeof(BItem) > B->o_items + bytes) { printf("op items out\n"); ++bad; }
-                if (o.kind >= 3 && o.off + (size_t)o.n * sizeof(BCopy) > B->o_items + bytes) { printf("op copies out\n"); ++bad; }
+                if (o.kind <= 1 && o.off + (size_t)o.n * sizeof(BItem) > B->o_items + bytes) { REPORT("op items out\n"); ++bad; }
+                if (o.kind >= 3 && o.off + (size_t)o.n * sizeof(BCopy) > B->o_items + bytes) { REPORT("op copies out\n"); ++bad; }
             }
-            if (verbose) printf("od=%d gm=%d: %zu items, %zu copies, %zu ops, %zu bytes (cap %zu)\n", od, gm,
+            if (verbose) REPORT("od=%d gm=%d: %zu items, %zu copies, %zu ops, %zu bytes (cap %zu)\n", od, gm,
                                 bd.items.size(), bd.copies.size(), ops.size(), bytes, B->items_cap);
         }
     B->ws = nullptr;
